@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the MXE hot path on one MI355X.
+
+A step is one diffusion step of the staggered scheme on the 256,000-site FCC
+vacancy system (40^3 periodic cells, 1% vacancies, T = 1000 K, 27-node
+quadrature, <= 30 FIRE updates per relaxation): neighbour-list maintenance,
+relaxation (pair quadrature, density pass, force/mu pass, FIRE), master-
+equation flux, time step and Euler update, all on the GPU.
+
+Prints ONE JSON line. `value` = site-quadrature evaluations per second over the
+timed steps (sites x evaluations / wall time), with every input resident in HBM.
+The roofline entry reports the dominant kernel against MI355X peak, from HIP
+events bracketing its launches on the launch stream during the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "site-quadrature evals/s + master-eq site-steps/s; mixed/batched vs FP64 plain"
+PEAK_HBM_GBS = 8000.0
+# FP64 vector: 256 CUs x 64 FP64 lanes/clock x 2.4 GHz = 39.3e12 lane-operations/s
+# (78.6 TFLOP/s counting a fused multiply-add as two flops).
+PEAK_FP64_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic work of one pair quadrature: 27 nodes x 90 FP64 operations (two
+# exponentials, square root, reciprocal, taper and ~30 multiply-adds for the
+# values, gradients and width derivatives of both radial shapes).
+OPS_PER_PAIR = 27 * 90
+# Algorithmic HBM bytes of the force/mu gather: each pair's 14 FP64 moments and
+# its row entry (neighbour index, pair id) are read from both ends; per site the
+# state, embedding terms, FIRE velocity and the six outputs.
+BYTES_FORCE_PER_PAIR = 2 * (14 * 8 + 8)
+BYTES_FORCE_PER_SITE = 8 + 8 + 1 + 8 * 3 + 8 * 4 + 8 * 6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(workload, n_sample: int):
+    """The CPU oracle timed on a bounded sample of the same state."""
+    import numpy as np
+
+    import oracle as O
+    s = workload.systems[0]
+    sel = np.arange(n_sample, dtype=np.int32)
+    O.lib()
+    t0 = time.perf_counter()
+    O.evaluate_sites(workload.eam, s.box, s.periodic, s.T, s.q, s.sigma, s.x, s.type, sel)
+    dt = time.perf_counter() - t0
+    return dict(value=n_sample / dt, unit="site-evals/s", cores=O.num_threads(), kind="oracle",
+                sample=f"one evaluation (density pass over the sample and its neighbours, force/mu "
+                       f"pass over the sample) of the first {n_sample} of {s.n} sites of the "
+                       f"initial state; {dt:.2f} s wall")
+
+
+def timed_run(plan, st, out, ws, steps, use_graph, profile):
+    import torch
+    plan.profile(profile)
+    if profile:
+        plan.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(st, out, ws, steps, use_graph=use_graph)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = plan.profile_read() if profile else None
+    plan.profile(False)
+    sc = plan.scalars(out)[0]
+    return wall, sc, prof
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=24576)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the graph and FP32 legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1910_01235_amd import lattice as L
+    from paper_1910_01235_amd import mxe
+
+    torch.cuda.set_device(0)
+    w = L.config1(1)
+    s = w.systems[0]
+    n = s.n
+    n_mobile = int((s.type != L.HOST_FIXED).sum())
+    log(f"workload {w.name}: {n} sites, warmup {args.warmup}, steps {args.steps}")
+
+    plan = mxe.Plan([s], w.eam, w.params, precision="fp64")
+    st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+    plan.run(st, out, ws, args.warmup, use_graph=True)
+    torch.cuda.synchronize()
+    log(f"warmup done: status {int(plan.scalars(out)[0, mxe.S_STATUS])}")
+
+    wall, sc, prof = timed_run(plan, st, out, ws, args.steps, use_graph=False, profile=True)
+    evals = int(sc[mxe.S_TOTAL_EVALS])
+    pair_evals = float(sc[mxe.S_PAIR_EVALS])
+    status = int(sc[mxe.S_STATUS])
+    value = n * evals / wall
+    site_steps = n_mobile * args.steps / wall
+    log(f"timed: {wall:.3f} s, {evals} evaluations, status {status}")
+
+    # roofline of each hot kernel family
+    fam = {}
+    for k, (ms, cnt) in prof.items():
+        fam[k] = dict(ms_total=ms, launches=cnt, ms_avg=(ms / cnt if cnt else 0.0))
+    pairs_per_launch = pair_evals / max(fam["pair"]["launches"], 1)
+    ops = OPS_PER_PAIR * pairs_per_launch
+    pair_avg_s = fam["pair"]["ms_avg"] / 1e3
+    roof_pair = dict(bound="alu", achieved=ops / pair_avg_s / 1e12 if pair_avg_s > 0 else 0.0,
+                     peak=PEAK_FP64_TOPS, unit="Tops/s", kernel="k_pair<double>",
+                     traffic=None)
+    roof_pair["frac"] = roof_pair["achieved"] / roof_pair["peak"]
+    evals_per_launch = evals / max(fam["force"]["launches"], 1)
+    bytes_force = (BYTES_FORCE_PER_PAIR * pair_evals / max(evals, 1) + BYTES_FORCE_PER_SITE * n) \
+        * evals_per_launch
+    force_avg_s = fam["force"]["ms_avg"] / 1e3
+    roof_force = dict(bound="hbm", achieved=bytes_force / force_avg_s / 1e9 if force_avg_s > 0 else 0.0,
+                      peak=PEAK_HBM_GBS, unit="GB/s", kernel="k_force<double>", traffic=None)
+    roof_force["frac"] = roof_force["achieved"] / roof_force["peak"]
+    dominant = max(fam, key=lambda k: fam[k]["ms_total"])
+    roofline = roof_pair if dominant != "force" else roof_force
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "site-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "sites": n, "vacancies": int((s.x == 0).sum()),
+                   "T_K": s.T, "quadrature_nodes": 27, "max_relax": w.params["max_relax"],
+                   "precision": "fp64", "launch": "eager with per-kernel HIP events"},
+        "site_steps_per_s": site_steps,
+        "evals_in_timed_steps": evals,
+        "pairs_per_eval": pair_evals / max(evals, 1),
+        "status": status,
+        "roofline": roofline,
+        "roofline_all": {"pair": roof_pair, "force": roof_force},
+        "kernel_ms": fam,
+        "dominant_kernel": dominant,
+    }
+
+    if not args.no_extras:
+        wall_g, sc_g, _ = timed_run(plan, st, out, ws, args.steps, use_graph=True, profile=False)
+        result["graph"] = dict(value=n * int(sc_g[mxe.S_TOTAL_EVALS]) / wall_g,
+                               ms_per_step=wall_g / args.steps * 1e3,
+                               evals=int(sc_g[mxe.S_TOTAL_EVALS]))
+        log(f"graph leg: {wall_g:.3f} s")
+        del st, out, ws, plan
+        torch.cuda.empty_cache()
+        p32 = mxe.Plan([s], w.eam, w.params, precision="fp32")
+        st32, out32, ws32 = p32.state([s]), p32.out(), p32.workspace()
+        p32.run(st32, out32, ws32, args.warmup, use_graph=True)
+        wall_32, sc_32, prof32 = timed_run(p32, st32, out32, ws32, args.steps, use_graph=False,
+                                           profile=True)
+        ev32 = int(sc_32[mxe.S_TOTAL_EVALS])
+        result["fp32_mixed"] = dict(value=n * ev32 / wall_32, ms_per_step=wall_32 / args.steps * 1e3,
+                                    evals=ev32, status=int(sc_32[mxe.S_STATUS]),
+                                    kernel_ms={k: v[0] for k, v in prof32.items()})
+        log(f"fp32 leg: {wall_32:.3f} s")
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

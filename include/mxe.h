@@ -1,0 +1,250 @@
+/*
+ * mxe.h -- C ABI of the MI355X mean-field EAM + master-equation library.
+ *
+ * Method: Ponga et al., "MXE" (arXiv:1910.01235). The library evaluates the
+ * mean-field free energy of Sec. 2.1, Eq. (Grand-Canonical-Free-Energy), for
+ * the thermalised EAM of App. B.2 (Eqs. EAM_mxe, F_taylor_mxe) with site
+ * occupancies (App. B.2.1, Eqs. EAM-Substitutional-ave,
+ * EAM-density-substitutional-ave), phase averages by Gauss-Hermite quadrature
+ * (App. A, Eq. QuadRule; here the 27-node product rule on each pair's relative
+ * coordinate), relaxes positions and widths at fixed occupancy, and advances
+ * the occupancy field with the kinetic law of Sec. 3.1 (Eqs. MassTransport,
+ * attempt_freq_mass) by forward Euler in the staggered scheme of Sec. 4
+ * (Alg. 1). Inputs follow the paper's statement of the problem (Sec. 4 and
+ * the program summary): sites with mean positions, widths, species
+ * occupancies and a temperature; outputs are relaxed positions and widths,
+ * chemical potentials, dx/dt, the time step and the free energy.
+ *
+ * Conventions shared by every entry point
+ *   Units: eV, Angstrom, K, s.
+ *   Batches: a plan covers n_systems >= 1 independent systems whose sites are
+ *     concatenated in system order; every per-site array holds sum(n_sites)
+ *     entries. Systems never interact.
+ *   Ownership: the caller allocates and owns every device buffer (state,
+ *     outputs, workspace). The library never allocates device memory; a plan
+ *     owns host memory, one HIP stream used only to record graphs, and the
+ *     graphs it records. All device pointers must be valid for the current
+ *     HIP device.
+ *   Asynchrony: every call only enqueues work on `stream` (a hipStream_t
+ *     passed as void*, 0 = the null stream) and returns at once. Return codes
+ *     report argument and plan errors; errors the device detects are written
+ *     to the per-system status scalar, to be read after the stream syncs.
+ *   Determinism: no floating-point atomics; results are bitwise reproducible
+ *     run to run, and a system's results do not depend on the other systems
+ *     of its batch.
+ *   Errors: no exception or abort crosses the ABI. mxe_last_error() returns a
+ *     thread-local message for the last failing call of the calling thread.
+ *   Threads: calls on one plan must not overlap (a plan holds the workspace
+ *     binding and graph cache). Different plans are independent.
+ */
+#ifndef MXE_H
+#define MXE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MXE_OK = 0,
+    MXE_EINVAL = -1,   /* invalid argument or inconsistent plan            */
+    MXE_ENOMEM = -2,   /* workspace smaller than mxe_workspace_bytes()      */
+    MXE_EDEVICE = -3,  /* a HIP runtime call failed                         */
+    MXE_ERANGE = -5    /* a size limit of the plan would be exceeded        */
+} mxe_status;
+
+typedef enum { MXE_FP64 = 0, MXE_FP32_MIXED = 1 } mxe_precision;
+
+/* Site types. Each site holds its mobile species with probability x and the
+ * complement with 1 - x (Sec. 2, Eq. occupancy; App. B.2.1):
+ *   HOST_VAC      atom A or vacancy        (x = fraction of A)
+ *   ALLOY         species B or species A   (x = fraction of B)
+ *   INTERSTITIAL  solute S or empty        (x = fraction of S)
+ *   HOST_FIXED    atom A, x == 1, immobile                                   */
+typedef enum {
+    MXE_SITE_HOST_VAC = 0,
+    MXE_SITE_ALLOY = 1,
+    MXE_SITE_INTERSTITIAL = 2,
+    MXE_SITE_HOST_FIXED = 3
+} mxe_site_type;
+
+/* Analytic EAM (App. B.2): species A = 0, B = 1, S = 2; vacancy/empty carry
+ * nothing. Embedding F_k(rho) = -embed_c[k] sqrt(rho); species k emits density
+ * emit_b[k] g_f(r); pair energy a_kl g_phi(r). Radial shapes per pair class
+ * (0 host-host, 1 host-interstitial; interstitial pairs do not interact):
+ * g_phi = exp(-alpha (r/r_e - 1)) S(r), g_f = exp(-gamma (r/r_e - 1)) S(r),
+ * S = 1 below r_s, (1 + cos(pi (r - r_s)/(r_c - r_s)))/2 up to r_c, 0 beyond. */
+typedef struct {
+    double embed_c[3];
+    double emit_b[3];
+    double pair_a[3][3]; /* symmetric */
+    double r_e[2];
+    double alpha[2];
+    double gamma[2];
+    double r_s, r_c;
+} mxe_eam;
+
+typedef struct {
+    /* kinetic law: D = nu0 exp(-Qm / kT); rate factor exp(kin_c beta dmu)    */
+    double nu0, Qm, kin_c;
+    /* Euler step dt = dt_safety / (largest per-site outflow or inflow rate)   */
+    double dt_safety;
+    /* FIRE relaxation of (q, sigma) at fixed x                                */
+    int max_relax;       /* updates per relaxation; max_relax + 1 evaluations */
+    double ftol;         /* convergence: max |f| <= ftol (eV/A)               */
+    double fire_dt0, fire_dtmax, fire_alpha0, fire_finc, fire_fdec, fire_falpha;
+    int fire_nmin;
+    double sigma_min;    /* widths are clamped from below                     */
+    double sigma_cap;    /* widths above this flag MXE_STAT_SIGMA_CAP; sizes the cells */
+    double skin;         /* neighbour-list skin (A)                           */
+    double r_bond;       /* kinetic-law bond radius: same-type sites closer   */
+    int k_max;           /* neighbour-list row length (max neighbours/site)   */
+    int bond_max;        /* max bonds per site                                */
+    mxe_precision precision;
+} mxe_params;
+
+typedef struct {
+    int64_t n_sites;
+    double box[3];       /* periodic axis: period; open axis: extent [0, box) */
+    int periodic[3];
+    double T;            /* temperature (K), uniform over the system           */
+} mxe_system;
+
+/* Device buffers, SoA FP64, concatenated over systems. */
+typedef struct {
+    double* qx;
+    double* qy;
+    double* qz;
+    double* sigma;
+    double* x;
+    const int8_t* type;
+} mxe_state;
+
+/* Outputs. fx..fsigma are the occupancy-normalised forces -dF/dy / w_i that
+ * drive the relaxation (w = x on HOST_VAC and INTERSTITIAL sites, else 1).
+ * mu_i = d(F - E_mix)/dx_i (0 on HOST_FIXED sites). e_site sums to F.
+ * scalars: MXE_NSCALARS doubles per system, indexed by mxe_scalar. */
+typedef struct {
+    double* fx;
+    double* fy;
+    double* fz;
+    double* fsigma;
+    double* mu;
+    double* dxdt;
+    double* rho_bar;
+    double* rho0;
+    double* e_site;
+    double* scalars;
+} mxe_out;
+
+typedef enum {
+    MXE_S_F = 0,          /* free energy of the last evaluation (eV)           */
+    MXE_S_FMAX = 1,       /* max |f| over all DOF of the last evaluation        */
+    MXE_S_DT = 2,         /* last Euler time step (s)                           */
+    MXE_S_TIME = 3,       /* accumulated time; in/out, the caller sets it       */
+    MXE_S_SUMX = 4,       /* sum of x after the last step / at the last eval    */
+    MXE_S_UPDATES = 5,    /* FIRE updates of the last relaxation                */
+    MXE_S_CONVERGED = 6,  /* 1 if the last relaxation reached ftol              */
+    MXE_S_EVALS = 7,      /* evaluations of the last relaxation                 */
+    MXE_S_STATUS = 8,     /* OR of mxe_stat_bits since the call started         */
+    MXE_S_REBUILDS = 9,   /* neighbour-list builds during the call              */
+    MXE_S_TOTAL_EVALS = 10, /* evaluations during the call                       */
+    MXE_S_PAIRS = 11,     /* pairs in the current neighbour list                */
+    MXE_S_PAIR_EVALS = 12, /* pair quadratures (27 nodes each) during the call  */
+    MXE_NSCALARS = 16
+} mxe_scalar;
+
+typedef enum {
+    MXE_STAT_NONFINITE = 1,   /* non-finite force, energy or x               */
+    MXE_STAT_X_RANGE = 2,     /* x left [-1e-12, 1 + 1e-12]                   */
+    MXE_STAT_RHO = 4,         /* rho0 <= 0 on a site with an embedding        */
+    MXE_STAT_SIGMA_MIN = 8,   /* a width was clamped at sigma_min (warning)   */
+    MXE_STAT_KMAX = 16,       /* neighbour row overflow: results invalid      */
+    MXE_STAT_RESERVED = 32,   /* unused                                        */
+    MXE_STAT_PAIRS = 64,      /* pair buffer overflow: results invalid        */
+    MXE_STAT_BONDS = 128,     /* bond row overflow: results invalid           */
+    MXE_STAT_SIGMA_CAP = 256  /* a width exceeded sigma_cap: results invalid  */
+} mxe_stat_bits;
+
+typedef struct mxe_plan mxe_plan;
+
+/* Fill *p with the library defaults (FP64, FIRE constants of Bitzek et al.,
+ * kin_c = 1, dt_safety = 0.5, sigma_cap = 0.3, skin = 0.15, k_max = 96,
+ * bond_max = 16). */
+void mxe_default_params(mxe_params* p);
+
+/* Create a plan for n_systems systems. Validates sizes: every periodic box
+ * length must exceed twice the largest neighbour radius
+ * r_c + 3 sqrt(2) sigma_cap + skin. Returns MXE_EINVAL on bad input, with
+ * *out = NULL. The plan copies everything it needs from its arguments. */
+mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* eam, int n_systems,
+                           const mxe_system* systems, mxe_plan** out);
+
+void mxe_plan_destroy(mxe_plan* plan);
+
+/* Size in bytes of the device workspace the plan needs (a single buffer,
+ * 256-byte aligned by the caller's allocator). The workspace persists state
+ * between calls (neighbour lists, FIRE velocities): pass the same buffer to
+ * every call of a run. */
+mxe_status mxe_workspace_bytes(const mxe_plan* plan, size_t* bytes);
+
+/* Total number of sites of the plan (length of every per-site array). */
+int64_t mxe_plan_sites(const mxe_plan* plan);
+
+/* One evaluation at the current state: pass 1 (rho_bar, rho0, the Taylor
+ * embedding G, A, B of Eq. F_taylor_mxe) and pass 2 (forces, mu, e_site);
+ * writes F, FMAX, SUMX, PAIRS, STATUS scalars. Rebuilds the neighbour lists. */
+mxe_status mxe_evaluate(mxe_plan* plan, const mxe_state* state, const mxe_out* out, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* FIRE relaxation of (q, sigma) at fixed x (Sec. 4: the relaxation step of
+ * the staggered scheme), at most params.max_relax updates per system; the
+ * outputs hold the last evaluation. Systems relax independently. */
+mxe_status mxe_relax(mxe_plan* plan, const mxe_state* state, const mxe_out* out, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* One forward-Euler step of the kinetic law (Sec. 3.1, Sec. 4) using out->mu
+ * from the previous evaluation: writes dxdt, DT, adds DT to TIME, updates x
+ * on mobile sites and writes SUMX. dt_in > 0 forces that time step for every
+ * system; dt_in <= 0 uses the stable rule. Bonds (same-type sites closer than
+ * r_bond) are built from the current positions. */
+mxe_status mxe_step(mxe_plan* plan, const mxe_state* state, const mxe_out* out, double dt_in,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* n_steps diffusion steps of the staggered scheme (Alg. 1): per step relax
+ * at fixed x, then one Euler step of x with mu of the last evaluation. Bonds
+ * are built once at the start from the current positions. With use_graph != 0
+ * the per-step launch sequence is recorded once into a HIP graph (per plan,
+ * buffers and stream) and replayed. */
+mxe_status mxe_run(mxe_plan* plan, const mxe_state* state, const mxe_out* out, int n_steps,
+                   int use_graph, void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel families timed by the profiling switch. */
+typedef enum {
+    MXE_K_PAIR = 0,     /* pair quadrature: 27 nodes -> 14 moments per pair    */
+    MXE_K_DENSITY = 1,  /* density gather and Taylor embedding terms           */
+    MXE_K_FORCE = 2,    /* force / mu gather and chunk partial sums            */
+    MXE_K_BUILD = 3,    /* neighbour-list build chain (mostly early exits)     */
+    MXE_K_FIRE = 4,     /* FIRE control and update                             */
+    MXE_K_MASTER = 5,   /* master-equation flux, time step, Euler update       */
+    MXE_NPROF = 6
+} mxe_kernel;
+
+/* Profiling switch (instrumentation, not part of the method). With on != 0,
+ * later calls launch eagerly (mxe_run ignores use_graph) and bracket each
+ * launch of every kernel family with HIP events recorded on the launch
+ * stream. mxe_profile_read waits for those events and returns, per family,
+ * the summed duration in ms and the number of launches since the previous
+ * read (arrays of MXE_NPROF entries, caller-owned host memory). */
+mxe_status mxe_profile(mxe_plan* plan, int on);
+mxe_status mxe_profile_read(mxe_plan* plan, double* ms, int64_t* launches);
+
+const char* mxe_status_string(mxe_status s);
+const char* mxe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

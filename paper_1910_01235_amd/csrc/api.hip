@@ -1,0 +1,547 @@
+// C ABI implementation: plans, workspace layout, launch sequences, graphs.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mxe_internal.h"
+
+using namespace mxe;
+
+namespace {
+
+thread_local std::string g_err;
+
+mxe_status fail(mxe_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_OK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(MXE_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct mxe_plan {
+    mxe_params p;
+    mxe_eam e;
+    Model model;
+    int n_sys = 0;
+    std::vector<mxe_system> systems;
+    std::vector<SysDesc> sys;
+    std::vector<Chunk> chunks, pchunks;
+    int64_t n_sites = 0, n_cells = 0, pair_cap_total = 0;
+    // workspace layout (byte offsets)
+    size_t o_sys, o_ctl, o_chunks, o_pchunks, o_site_sys, o_cell_count, o_cell_start, o_cell_sites;
+    size_t o_cell_of, o_slot_of, o_chunk_up, o_chunk_off;
+    size_t o_nbr, o_cnt, o_lo, o_pid, o_hoff, o_pi, o_pj, o_fblk, o_dblk, o_G, o_A, o_B;
+    size_t o_v, o_qr, o_sref, o_bond, o_nbond, o_part;
+    size_t ws_bytes = 0;
+    // graph cache for mxe_run
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::vector<const void*> graph_key;
+    // profiling: event pairs bracketing launches, per kernel family
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_events;       // pool, reused after each read
+    std::vector<std::pair<int, size_t>> prof_marks;  // (family, index of start event)
+    hipError_t prof_err = hipSuccess;
+};
+
+extern "C" void mxe_default_params(mxe_params* p) {
+    std::memset(p, 0, sizeof(*p));
+    p->nu0 = 1.0e13;
+    p->Qm = 0.69;
+    p->kin_c = 1.0;
+    p->dt_safety = 0.5;
+    p->max_relax = 50;
+    p->ftol = 1.0e-3;
+    p->fire_dt0 = 0.05;
+    p->fire_dtmax = 0.15;
+    p->fire_alpha0 = 0.1;
+    p->fire_finc = 1.1;
+    p->fire_fdec = 0.5;
+    p->fire_falpha = 0.99;
+    p->fire_nmin = 5;
+    p->sigma_min = 0.01;
+    p->sigma_cap = 0.3;
+    p->skin = 0.15;
+    p->r_bond = 3.09;
+    p->k_max = 96;
+    p->bond_max = 16;
+    p->precision = MXE_FP64;
+}
+
+extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* eam, int n_systems,
+                                      const mxe_system* systems, mxe_plan** out) {
+    if (!out) return fail(MXE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params || !eam || !systems || n_systems < 1) return fail(MXE_EINVAL, "null argument or n_systems < 1");
+    const mxe_params& p = *params;
+    if (p.precision != MXE_FP64 && p.precision != MXE_FP32_MIXED) return fail(MXE_EINVAL, "bad precision");
+    if (p.k_max < 1 || p.k_max > 1024 || p.bond_max < 1 || p.max_relax < 0)
+        return fail(MXE_EINVAL, "bad k_max / bond_max / max_relax");
+    if (!(p.sigma_min > 0) || !(p.sigma_cap > p.sigma_min) || !(p.skin > 0) || !(p.dt_safety > 0) ||
+        !(p.r_bond > 0) || !(p.ftol >= 0) || !(p.fire_dt0 > 0) || !(p.fire_dtmax > 0))
+        return fail(MXE_EINVAL, "bad sigma_min / sigma_cap / skin / dt_safety / r_bond / ftol / FIRE steps");
+    if (!(eam->r_c > eam->r_s) || !(eam->r_s > 0)) return fail(MXE_EINVAL, "need 0 < r_s < r_c");
+    for (int c = 0; c < 2; ++c)
+        if (!(eam->r_e[c] > 0)) return fail(MXE_EINVAL, "r_e must be positive");
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l)
+            if (eam->pair_a[k][l] != eam->pair_a[l][k]) return fail(MXE_EINVAL, "pair_a must be symmetric");
+
+    mxe_plan* P = new mxe_plan();
+    P->p = p;
+    P->e = *eam;
+    P->n_sys = n_systems;
+    P->systems.assign(systems, systems + n_systems);
+
+    Model& m = P->model;
+    std::memset(&m, 0, sizeof(m));
+    for (int k = 0; k < 3; ++k) {
+        m.c4[k] = eam->embed_c[k];
+        m.b4[k] = eam->emit_b[k];
+        for (int l = 0; l < 3; ++l) m.a4[k][l] = eam->pair_a[k][l];
+    }
+    for (int c = 0; c < 2; ++c) {
+        m.r_e[c] = eam->r_e[c];
+        m.inv_re[c] = 1.0 / eam->r_e[c];
+        m.alpha[c] = eam->alpha[c];
+        m.gamma[c] = eam->gamma[c];
+    }
+    m.r_s = eam->r_s;
+    m.r_c = eam->r_c;
+    m.taper_inv_w = 1.0 / (eam->r_c - eam->r_s);
+    m.ftol = p.ftol;
+    m.dt0 = p.fire_dt0;
+    m.dtmax = p.fire_dtmax;
+    m.alpha0 = p.fire_alpha0;
+    m.finc = p.fire_finc;
+    m.fdec = p.fire_fdec;
+    m.falpha = p.fire_falpha;
+    m.nmin = p.fire_nmin;
+    m.max_relax = p.max_relax;
+    m.sigma_min = p.sigma_min;
+    m.sigma_cap = p.sigma_cap;
+    m.skin = p.skin;
+    m.r_bond = p.r_bond;
+    m.kin_c = p.kin_c;
+    m.dt_safety = p.dt_safety;
+
+    // largest list radius the cells must cover
+    const double r_cap = eam->r_c + 3.0 * std::sqrt(2.0) * p.sigma_cap + p.skin;
+    const double r_cell = std::max(r_cap, p.r_bond);
+    int64_t site_off = 0, cell_off = 0, pair_base = 0;
+    for (int s = 0; s < n_systems; ++s) {
+        const mxe_system& ms = systems[s];
+        if (ms.n_sites < 1) {
+            delete P;
+            return fail(MXE_EINVAL, "system " + std::to_string(s) + ": n_sites < 1");
+        }
+        if (!(ms.T > 0)) {
+            delete P;
+            return fail(MXE_EINVAL, "system " + std::to_string(s) + ": T must be positive");
+        }
+        SysDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.site_off = site_off;
+        d.n_sites = ms.n_sites;
+        int64_t ncell = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (!(ms.box[a] > 0)) {
+                delete P;
+                return fail(MXE_EINVAL, "system " + std::to_string(s) + ": box lengths must be positive");
+            }
+            d.box[a] = ms.box[a];
+            d.periodic[a] = ms.periodic[a] ? 1 : 0;
+            if (d.periodic[a] && !(ms.box[a] > 2.0 * r_cap)) {
+                delete P;
+                return fail(MXE_EINVAL, "system " + std::to_string(s) +
+                                            ": periodic box length must exceed twice the list radius " +
+                                            std::to_string(r_cap));
+            }
+            int nc = (int)std::floor(ms.box[a] / r_cell);
+            nc = std::max(1, std::min(nc, 1024));
+            d.nc[a] = nc;
+            d.cell_w[a] = ms.box[a] / nc;
+            ncell *= nc;
+        }
+        d.cell_off = cell_off;
+        d.n_cells = ncell;
+        d.pair_base = pair_base;
+        d.pair_cap = (ms.n_sites * (int64_t)p.k_max + 1) / 2;
+        d.kT = kBoltzmannEv * ms.T;
+        d.beta = 1.0 / d.kT;
+        d.D = p.nu0 * std::exp(-d.beta * p.Qm);
+        d.chunk_first = (int)P->chunks.size();
+        for (int64_t a = 0; a < ms.n_sites; a += kChunk) {
+            Chunk c{s, (int)(site_off + a), (int)(site_off + std::min<int64_t>(ms.n_sites, a + kChunk)), 0};
+            P->chunks.push_back(c);
+        }
+        d.n_chunks = (int)P->chunks.size() - d.chunk_first;
+        for (int64_t a = 0; a < d.pair_cap; a += kPairChunk) {
+            Chunk c{s, (int)(pair_base + a), (int)(pair_base + std::min<int64_t>(d.pair_cap, a + kPairChunk)), 0};
+            P->pchunks.push_back(c);
+        }
+        P->sys.push_back(d);
+        site_off += ms.n_sites;
+        cell_off += ncell;
+        pair_base += d.pair_cap;
+    }
+    P->n_sites = site_off;
+    P->n_cells = cell_off;
+    P->pair_cap_total = pair_base;
+    if (site_off * (int64_t)p.k_max >= (int64_t)INT32_MAX || pair_base >= (int64_t)INT32_MAX ||
+        cell_off >= (int64_t)INT32_MAX) {
+        delete P;
+        return fail(MXE_ERANGE, "plan too large for 32-bit indices");
+    }
+
+    // workspace layout
+    const size_t A = 256;
+    const int64_t N = P->n_sites;
+    const size_t mom_elt = p.precision == MXE_FP32_MIXED ? sizeof(float) : sizeof(double);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = align_up(o + bytes, A);
+        return r;
+    };
+    P->o_sys = take(sizeof(SysDesc) * n_systems);
+    P->o_ctl = take(sizeof(SysCtl) * n_systems);
+    P->o_chunks = take(sizeof(Chunk) * P->chunks.size());
+    P->o_pchunks = take(sizeof(Chunk) * P->pchunks.size());
+    P->o_site_sys = take(sizeof(int) * N);
+    P->o_cell_count = take(sizeof(int) * P->n_cells);
+    P->o_cell_start = take(sizeof(int) * P->n_cells);
+    P->o_cell_sites = take(sizeof(int) * N);
+    P->o_cell_of = take(sizeof(int) * N);
+    P->o_slot_of = take(sizeof(int) * N);
+    P->o_chunk_up = take(sizeof(int) * P->chunks.size());
+    P->o_chunk_off = take(sizeof(int) * P->chunks.size());
+    P->o_nbr = take(sizeof(int) * N * p.k_max);
+    P->o_cnt = take(sizeof(int) * N);
+    P->o_lo = take(sizeof(int) * N);
+    P->o_pid = take(sizeof(int) * N * p.k_max);
+    P->o_hoff = take(sizeof(int) * N);
+    P->o_pi = take(sizeof(int) * P->pair_cap_total);
+    P->o_pj = take(sizeof(int) * P->pair_cap_total);
+    P->o_fblk = take(mom_elt * kFBlk * P->pair_cap_total);
+    P->o_dblk = take(mom_elt * 2 * P->pair_cap_total);
+    P->o_G = take(sizeof(double) * N);
+    P->o_A = take(sizeof(double) * N);
+    P->o_B = take(sizeof(double) * N);
+    P->o_v = take(sizeof(double) * 4 * N);
+    P->o_qr = take(sizeof(double) * 3 * N);
+    P->o_sref = take(sizeof(double) * N);
+    P->o_bond = take(sizeof(int) * N * p.bond_max);
+    P->o_nbond = take(sizeof(int) * N);
+    P->o_part = take(sizeof(double) * kNPart * P->chunks.size());
+    P->ws_bytes = o;
+    *out = P;
+    return MXE_OK;
+}
+
+extern "C" void mxe_plan_destroy(mxe_plan* plan) {
+    if (!plan) return;
+    for (hipEvent_t e : plan->prof_events) (void)hipEventDestroy(e);
+    if (plan->graph) (void)hipGraphExecDestroy(plan->graph);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    delete plan;
+}
+
+extern "C" mxe_status mxe_workspace_bytes(const mxe_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return fail(MXE_EINVAL, "null argument");
+    *bytes = plan->ws_bytes;
+    return MXE_OK;
+}
+
+extern "C" int64_t mxe_plan_sites(const mxe_plan* plan) { return plan ? plan->n_sites : 0; }
+
+namespace {
+
+mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, void* ws,
+                    size_t ws_bytes, Dev* d) {
+    if (!st || !out || !ws) return fail(MXE_EINVAL, "null state, out or workspace");
+    if (ws_bytes < P->ws_bytes)
+        return fail(MXE_ENOMEM, "workspace has " + std::to_string(ws_bytes) + " bytes, plan needs " +
+                                    std::to_string(P->ws_bytes));
+    if (((uintptr_t)ws) % 256 != 0) return fail(MXE_EINVAL, "workspace must be 256-byte aligned");
+    const void* need[] = {st->qx, st->qy, st->qz, st->sigma, st->x, st->type, out->fx, out->fy,
+                          out->fz, out->fsigma, out->mu, out->dxdt, out->rho_bar, out->rho0,
+                          out->e_site, out->scalars};
+    for (const void* q : need)
+        if (!q) return fail(MXE_EINVAL, "a state or output pointer is NULL");
+    char* w = (char*)ws;
+    Dev& D = *d;
+    std::memset(&D, 0, sizeof(D));
+    D.qx = st->qx;
+    D.qy = st->qy;
+    D.qz = st->qz;
+    D.sigma = st->sigma;
+    D.x = st->x;
+    D.type = st->type;
+    D.fx = out->fx;
+    D.fy = out->fy;
+    D.fz = out->fz;
+    D.fs = out->fsigma;
+    D.mu = out->mu;
+    D.dxdt = out->dxdt;
+    D.rho_bar = out->rho_bar;
+    D.rho0 = out->rho0;
+    D.e_site = out->e_site;
+    D.scalars = out->scalars;
+    const int64_t N = P->n_sites;
+    D.sys = (SysDesc*)(w + P->o_sys);
+    D.ctl = (SysCtl*)(w + P->o_ctl);
+    D.chunks = (Chunk*)(w + P->o_chunks);
+    D.pchunks = (Chunk*)(w + P->o_pchunks);
+    D.site_sys = (int*)(w + P->o_site_sys);
+    D.cell_count = (int*)(w + P->o_cell_count);
+    D.cell_start = (int*)(w + P->o_cell_start);
+    D.cell_sites = (int*)(w + P->o_cell_sites);
+    D.cell_of = (int*)(w + P->o_cell_of);
+    D.slot_of = (int*)(w + P->o_slot_of);
+    D.chunk_up = (int*)(w + P->o_chunk_up);
+    D.chunk_off = (int*)(w + P->o_chunk_off);
+    D.nbr = (int*)(w + P->o_nbr);
+    D.nbr_cnt = (int*)(w + P->o_cnt);
+    D.nbr_lo = (int*)(w + P->o_lo);
+    D.pid = (int*)(w + P->o_pid);
+    D.half_off = (int*)(w + P->o_hoff);
+    D.pair_i = (int*)(w + P->o_pi);
+    D.pair_j = (int*)(w + P->o_pj);
+    D.fblk = (void*)(w + P->o_fblk);
+    D.dblk = (void*)(w + P->o_dblk);
+    D.G = (double*)(w + P->o_G);
+    D.Ahat = (double*)(w + P->o_A);
+    D.Bhat = (double*)(w + P->o_B);
+    double* v = (double*)(w + P->o_v);
+    D.vx = v;
+    D.vy = v + N;
+    D.vz = v + 2 * N;
+    D.vs = v + 3 * N;
+    double* qr = (double*)(w + P->o_qr);
+    D.qrx = qr;
+    D.qry = qr + N;
+    D.qrz = qr + 2 * N;
+    D.sref = (double*)(w + P->o_sref);
+    D.bond = (int*)(w + P->o_bond);
+    D.nbond = (int*)(w + P->o_nbond);
+    D.part = (double*)(w + P->o_part);
+    D.n_sites = (int)N;
+    D.n_sys = P->n_sys;
+    D.n_chunks = (int)P->chunks.size();
+    D.n_pchunks = (int)P->pchunks.size();
+    D.K = P->p.k_max;
+    D.bond_max = P->p.bond_max;
+    D.n_cells = P->n_cells;
+    D.pair_cap_total = P->pair_cap_total;
+    return MXE_OK;
+}
+
+// Tables are re-uploaded at every call so a workspace needs no separate setup.
+mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, bool bonds) {
+    HIP_OK(hipMemcpyAsync(d.sys, P->sys.data(), sizeof(SysDesc) * P->sys.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d.chunks, P->chunks.data(), sizeof(Chunk) * P->chunks.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d.pchunks, P->pchunks.data(), sizeof(Chunk) * P->pchunks.size(),
+                          hipMemcpyHostToDevice, s));
+    launch_ws_init(d, s);
+    launch_sys_init(d, P->model, s);
+    launch_build(d, P->model, bonds, s);
+    HIP_OK(hipGetLastError());
+    return MXE_OK;
+}
+
+// Runs `launch` on stream s; with profiling on, brackets it with two events.
+template <typename F>
+void timed(mxe_plan* P, int family, hipStream_t s, F&& launch) {
+    if (!P->prof_on) {
+        launch();
+        return;
+    }
+    const size_t used = P->prof_marks.size() * 2;
+    while (P->prof_events.size() < used + 2) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            P->prof_err = r;
+            launch();
+            return;
+        }
+        P->prof_events.push_back(e);
+    }
+    hipError_t r1 = hipEventRecord(P->prof_events[used], s);
+    launch();
+    hipError_t r2 = hipEventRecord(P->prof_events[used + 1], s);
+    if (r1 != hipSuccess || r2 != hipSuccess) {
+        P->prof_err = r1 != hipSuccess ? r1 : r2;
+        return;
+    }
+    P->prof_marks.push_back({family, used});
+}
+
+void enqueue_eval(mxe_plan* P, const Dev& d, hipStream_t s) {
+    const int prec = P->p.precision;
+    timed(P, MXE_K_PAIR, s, [&] { launch_pair(d, P->model, prec, s); });
+    timed(P, MXE_K_DENSITY, s, [&] { launch_density(d, P->model, prec, s); });
+    timed(P, MXE_K_FORCE, s, [&] { launch_force(d, P->model, prec, s); });
+}
+
+void enqueue_iteration(mxe_plan* P, const Dev& d, hipStream_t s) {
+    timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, s); });
+    enqueue_eval(P, d, s);
+    timed(P, MXE_K_FIRE, s, [&] {
+        launch_control(d, P->model, 1, s);
+        launch_update(d, P->model, s);
+    });
+}
+
+void enqueue_relax(mxe_plan* P, const Dev& d, hipStream_t s) {
+    launch_relax_init(d, P->model, s);
+    for (int k = 0; k <= P->p.max_relax; ++k) enqueue_iteration(P, d, s);
+}
+
+void enqueue_diffusion_step(mxe_plan* P, const Dev& d, hipStream_t s) {
+    enqueue_relax(P, d, s);
+    timed(P, MXE_K_MASTER, s, [&] { launch_master(d, P->model, 0.0, s); });
+}
+
+}  // namespace
+
+extern "C" mxe_status mxe_evaluate(mxe_plan* P, const mxe_state* st, const mxe_out* out, void* ws,
+                                   size_t ws_bytes, void* stream) {
+    if (!P) return fail(MXE_EINVAL, "null plan");
+    Dev d;
+    mxe_status r = make_dev(P, st, out, ws, ws_bytes, &d);
+    if (r != MXE_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    r = begin_call(P, d, s, false);
+    if (r != MXE_OK) return r;
+    launch_relax_init(d, P->model, s);
+    enqueue_eval(P, d, s);
+    launch_control(d, P->model, 0, s);
+    HIP_OK(hipGetLastError());
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_relax(mxe_plan* P, const mxe_state* st, const mxe_out* out, void* ws,
+                                size_t ws_bytes, void* stream) {
+    if (!P) return fail(MXE_EINVAL, "null plan");
+    Dev d;
+    mxe_status r = make_dev(P, st, out, ws, ws_bytes, &d);
+    if (r != MXE_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    r = begin_call(P, d, s, false);
+    if (r != MXE_OK) return r;
+    enqueue_relax(P, d, s);
+    HIP_OK(hipGetLastError());
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_step(mxe_plan* P, const mxe_state* st, const mxe_out* out, double dt_in,
+                               void* ws, size_t ws_bytes, void* stream) {
+    if (!P) return fail(MXE_EINVAL, "null plan");
+    if (!std::isfinite(dt_in)) return fail(MXE_EINVAL, "dt_in must be finite");
+    Dev d;
+    mxe_status r = make_dev(P, st, out, ws, ws_bytes, &d);
+    if (r != MXE_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    r = begin_call(P, d, s, true);
+    if (r != MXE_OK) return r;
+    timed(P, MXE_K_MASTER, s, [&] { launch_master(d, P->model, dt_in, s); });
+    HIP_OK(hipGetLastError());
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* out, int n_steps,
+                              int use_graph, void* ws, size_t ws_bytes, void* stream) {
+    if (!P) return fail(MXE_EINVAL, "null plan");
+    if (n_steps < 0) return fail(MXE_EINVAL, "n_steps < 0");
+    Dev d;
+    mxe_status r = make_dev(P, st, out, ws, ws_bytes, &d);
+    if (r != MXE_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    r = begin_call(P, d, s, true);
+    if (r != MXE_OK) return r;
+    if (!use_graph || P->prof_on) {
+        for (int k = 0; k < n_steps; ++k) enqueue_diffusion_step(P, d, s);
+        HIP_OK(hipGetLastError());
+        return MXE_OK;
+    }
+    std::vector<const void*> key = {st->qx, st->qy, st->qz, st->sigma, st->x, st->type, out->fx, out->fy,
+                                    out->fz, out->fsigma, out->mu, out->dxdt, out->rho_bar, out->rho0,
+                                    out->e_site, out->scalars, ws};
+    if (!P->graph || key != P->graph_key) {
+        if (P->graph) {
+            HIP_OK(hipGraphExecDestroy(P->graph));
+            P->graph = nullptr;
+        }
+        if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
+        enqueue_diffusion_step(P, d, P->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e1 = hipStreamEndCapture(P->cap_stream, &g);
+        if (e1 != hipSuccess) return fail(MXE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e1));
+        hipError_t e2 = hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            P->graph = nullptr;
+            return fail(MXE_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
+        }
+        P->graph_key = key;
+    }
+    for (int k = 0; k < n_steps; ++k) HIP_OK(hipGraphLaunch(P->graph, s));
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_profile(mxe_plan* P, int on) {
+    if (!P) return fail(MXE_EINVAL, "null plan");
+    P->prof_on = on != 0;
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_profile_read(mxe_plan* P, double* ms, int64_t* launches) {
+    if (!P || !ms || !launches) return fail(MXE_EINVAL, "null argument");
+    for (int k = 0; k < MXE_NPROF; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    if (P->prof_err != hipSuccess) {
+        const hipError_t e = P->prof_err;
+        P->prof_err = hipSuccess;
+        P->prof_marks.clear();
+        return fail(MXE_EDEVICE, std::string("profiling event: ") + hipGetErrorString(e));
+    }
+    for (const auto& mk : P->prof_marks) {
+        HIP_OK(hipEventSynchronize(P->prof_events[mk.second + 1]));
+        float t = 0.0f;
+        HIP_OK(hipEventElapsedTime(&t, P->prof_events[mk.second], P->prof_events[mk.second + 1]));
+        ms[mk.first] += (double)t;
+        launches[mk.first] += 1;
+    }
+    P->prof_marks.clear();
+    return MXE_OK;
+}
+
+extern "C" const char* mxe_status_string(mxe_status s) {
+    switch (s) {
+        case MXE_OK: return "ok";
+        case MXE_EINVAL: return "invalid argument";
+        case MXE_ENOMEM: return "workspace too small";
+        case MXE_EDEVICE: return "HIP runtime error";
+        case MXE_ERANGE: return "size limit exceeded";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* mxe_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,171 @@
+// Internal definitions shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mxe.h"
+
+namespace mxe {
+
+constexpr int kMom = 14;            // moments computed per pair (see pair kernel)
+constexpr int kFBlk = 16;           // force block per pair: 14 moments + 2 pad = one 128-byte line (FP64)
+constexpr int kChunk = 256;         // sites per site-chunk; block size of per-site kernels
+constexpr int kPairChunk = 4096;    // pair slots per pair-chunk
+constexpr int kNPart = 8;           // partial sums per site-chunk
+constexpr int kWave = 64;
+constexpr double kBoltzmannEv = 8.617333262e-5;  // eV/K
+
+// moment slots of a pair, computed at rbar = q_hi - q_lo; this is also the
+// layout of the pair's force block (slots 14, 15 unused)
+enum {
+    M_PHI = 0, M_GPHI = 1, M_SPHI = 4,   // <phi>, grad <phi> (3), (d<phi>/ds)/s
+    M_F = 5, M_GF = 6, M_SF = 9,         // <f>, grad <f> (3), (d<f>/ds)/s
+    M_F0 = 10, M_GF0 = 11                // f(|rbar|), grad f(|rbar|) (3)
+};
+
+// partial-sum slots of a site-chunk
+enum { P_E = 0, P_FMAX = 1, P_FV = 2, P_FF = 3, P_VV = 4, P_SUMX = 5, P_RATE = 6 };
+
+struct SysDesc {
+    int64_t site_off, n_sites;
+    int64_t cell_off, n_cells;
+    int64_t pair_base, pair_cap;
+    double box[3];
+    double cell_w[3];
+    int nc[3];
+    int periodic[3];
+    double kT, beta, D;
+    int chunk_first, n_chunks;
+};
+
+struct SysCtl {
+    double fire_dt, fire_alpha;
+    double c_keep, mix_v, mix_f;
+    unsigned long long sigmax_bits;
+    double dt_master;
+    int npos, k, done, converged, updates, evals;
+    int rebuild, n_rebuilds, total_evals;
+    double pair_evals;
+    int n_pairs;
+    int status;
+    int pad;
+};
+
+struct Chunk {
+    int sys;
+    int start;  // first global index
+    int end;    // one past the last global index
+    int pad;
+};
+
+// Analytic EAM and run parameters, passed by value to the kernels.
+struct Model {
+    double c4[4], b4[4];    // per species (A, B, S, none): embedding strength, emission
+    double a4[4][4];        // pair amplitude, zero row/column for "none"
+    double r_e[2], inv_re[2], alpha[2], gamma[2];
+    double r_s, r_c, taper_inv_w;
+    double ftol, dt0, dtmax, alpha0, finc, fdec, falpha;
+    int nmin, max_relax;
+    double sigma_min, sigma_cap, skin, r_bond, kin_c, dt_safety;
+};
+
+// Every device pointer the kernels use.
+struct Dev {
+    // state
+    double *qx, *qy, *qz, *sigma, *x;
+    const int8_t* type;
+    // outputs
+    double *fx, *fy, *fz, *fs, *mu, *dxdt, *rho_bar, *rho0, *e_site, *scalars;
+    // workspace
+    SysDesc* sys;
+    SysCtl* ctl;
+    Chunk* chunks;
+    Chunk* pchunks;
+    int* site_sys;
+    int* cell_count;   // sites per cell (zero between builds)
+    int* cell_start;   // first entry of each cell in cell_sites
+    int* cell_sites;   // site indices grouped by cell, N entries
+    int *cell_of, *slot_of;
+    int *chunk_up, *chunk_off;
+    int *nbr, *nbr_cnt, *nbr_lo, *pid, *half_off;
+    int *pair_i, *pair_j;
+    void* fblk;   // [pair][kFBlk] force blocks (T)
+    void* dblk;   // [pair][2] density pair (<f>, f0) (T)
+    double *G, *Ahat, *Bhat;
+    double *vx, *vy, *vz, *vs;
+    double *qrx, *qry, *qrz, *sref;
+    int *bond, *nbond;
+    double* part;
+    int n_sites, n_sys, n_chunks, n_pchunks;
+    int K, bond_max;
+    int64_t n_cells, pair_cap_total;
+};
+
+// ---------------------------------------------------------------------------
+// Site occupancy model: a site holds species sp1 with probability p1 = x (1 for a
+// fixed host atom) and species sp0 with 1 - p1. Species 3 is "nothing".
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int occ_sp1(int t) { return t == MXE_SITE_ALLOY ? 1 : (t == MXE_SITE_INTERSTITIAL ? 2 : 0); }
+__host__ __device__ inline int occ_sp0(int t) { return t == MXE_SITE_ALLOY ? 0 : 3; }
+__host__ __device__ inline double occ_p1(int t, double x) { return t == MXE_SITE_HOST_FIXED ? 1.0 : x; }
+__host__ __device__ inline bool occ_mobile(int t) { return t != MXE_SITE_HOST_FIXED; }
+__host__ __device__ inline bool occ_partial(int t) {  // vibrating fraction w = x
+    return t == MXE_SITE_HOST_VAC || t == MXE_SITE_INTERSTITIAL;
+}
+__host__ __device__ inline bool is_inter(int t) { return t == MXE_SITE_INTERSTITIAL; }
+// interaction class of a pair: 0 host-host, 1 host-interstitial, -1 none
+__host__ __device__ inline int pair_cls(int ti, int tj) {
+    const bool a = is_inter(ti), b = is_inter(tj);
+    return (a && b) ? -1 : ((a || b) ? 1 : 0);
+}
+
+// per-species value mixed by the site's occupancy
+__device__ inline double mixval(const double* v4, int t, double x) {
+    const double p = occ_p1(t, x);
+    return p * v4[occ_sp1(t)] + (1.0 - p) * v4[occ_sp0(t)];
+}
+// the same divided by the vibrating fraction w (closed form)
+__device__ inline double mixhat(const double* v4, int t, double x) {
+    return occ_partial(t) ? v4[occ_sp1(t)] : mixval(v4, t, x);
+}
+__device__ inline double mixdx(const double* v4, int t) {
+    return occ_mobile(t) ? v4[occ_sp1(t)] - v4[occ_sp0(t)] : 0.0;
+}
+
+// index ranges for grid-stride loops
+__device__ inline int gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ inline int gstride() { return gridDim.x * blockDim.x; }
+
+// binary search for the system that owns global index `idx` given an
+// ascending offset field (site_off or cell_off)
+__device__ inline int find_sys_cell(const SysDesc* sys, int n_sys, int64_t idx) {
+    int lo = 0, hi = n_sys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sys[mid].cell_off <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (each defined next to its kernels).
+// ---------------------------------------------------------------------------
+void launch_ws_init(const Dev& d, hipStream_t s);
+void launch_sys_init(const Dev& d, const Model& m, hipStream_t s);
+void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s);
+void launch_relax_init(const Dev& d, const Model& m, hipStream_t s);
+void launch_pair(const Dev& d, const Model& m, int precision, hipStream_t s);
+void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s);
+void launch_force(const Dev& d, const Model& m, int precision, hipStream_t s);
+void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s);
+void launch_update(const Dev& d, const Model& m, hipStream_t s);
+void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s);
+
+}  // namespace mxe

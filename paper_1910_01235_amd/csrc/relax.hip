@@ -1,0 +1,286 @@
+// Relaxation control (FIRE) and the master-equation step.
+//
+// Relaxation (Sec. 4): positions and widths move at fixed x to lower the
+// mean-field free energy. The relaxer is FIRE (Bitzek et al., PRL 97, 170201,
+// 2006) with unit mass and semi-implicit Euler steps on the normalised forces.
+// Each system keeps its own FIRE scalars; a system that has converged (or hit
+// the iteration cap) is marked done and every later kernel skips it, so a
+// fixed launch sequence of max_relax + 1 iterations serves every system.
+//
+// Kinetic law (Sec. 3.1, Eq. MassTransport with Eq. attempt_freq_mass): the
+// flux over a bond is evaluated once per direction from the pair's canonical
+// (lower index, higher index) order, so the two ends receive exactly opposite
+// contributions and sum(x) is conserved up to the rounding of the Euler sums.
+// Time step: dt_safety over the largest per-site outflow or inflow rate,
+// weighted by the occupancy that can move, which keeps x inside [0, 1].
+#include "mxe_internal.h"
+
+namespace mxe {
+
+namespace {
+
+// Fixed-order block reductions over kChunk threads (deterministic).
+__device__ inline double block_sum(double v, double* lds) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = lds[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
+    return t;
+}
+__device__ inline double block_max(double v, double* lds) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = lds[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, lds[w]);
+    return t;
+}
+
+__device__ inline double* sc(const Dev& d, int s) { return d.scalars + (int64_t)s * MXE_NSCALARS; }
+
+}  // namespace
+
+__global__ void k_relax_init(Dev d, Model m) {
+    const int s = gtid();
+    if (s >= d.n_sys) return;
+    SysCtl& c = d.ctl[s];
+    c.fire_dt = m.dt0;
+    c.fire_alpha = m.alpha0;
+    c.npos = 0;
+    c.k = 0;
+    c.done = 0;
+    c.converged = 0;
+    c.updates = 0;
+    c.evals = 0;
+}
+
+void launch_relax_init(const Dev& d, const Model& m, hipStream_t s) {
+    k_relax_init<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d, m);
+}
+
+// One block per system: reduce the chunk partials in chunk order, then run
+// the FIRE decision (mode 1) or only record the evaluation (mode 0).
+__global__ __launch_bounds__(kChunk) void k_control(Dev d, Model m, int mode) {
+    __shared__ double lds[kChunk / kWave];
+    const int s = blockIdx.x;
+    SysCtl& c = d.ctl[s];
+    if (c.done) return;
+    const SysDesc& S = d.sys[s];
+    double e = 0.0, fm = 0.0, fv = 0.0, ff = 0.0, vv = 0.0, sx = 0.0;
+    for (int k = threadIdx.x; k < S.n_chunks; k += blockDim.x) {
+        const double* P = d.part + (int64_t)(S.chunk_first + k) * kNPart;
+        e += P[P_E];
+        fm = fmax(fm, P[P_FMAX]);
+        fv += P[P_FV];
+        ff += P[P_FF];
+        vv += P[P_VV];
+        sx += P[P_SUMX];
+    }
+    e = block_sum(e, lds);
+    fm = block_max(fm, lds);
+    fv = block_sum(fv, lds);
+    ff = block_sum(ff, lds);
+    vv = block_sum(vv, lds);
+    sx = block_sum(sx, lds);
+    if (threadIdx.x != 0) return;
+    double* out = sc(d, s);
+    c.evals += 1;
+    c.total_evals += 1;
+    c.pair_evals += (double)c.n_pairs;
+    out[MXE_S_PAIR_EVALS] = c.pair_evals;
+    out[MXE_S_F] = e;
+    out[MXE_S_FMAX] = fm;
+    out[MXE_S_SUMX] = sx;
+    out[MXE_S_TOTAL_EVALS] = (double)c.total_evals;
+    if (!isfinite(e) || !isfinite(ff)) c.status |= MXE_STAT_NONFINITE;
+    if (mode == 1) {
+        if (fm <= m.ftol) {
+            c.done = 1;
+            c.converged = 1;
+        } else if (c.k >= m.max_relax || (c.status & MXE_STAT_NONFINITE)) {
+            c.done = 1;
+        } else {
+            double dt = c.fire_dt, alpha = c.fire_alpha;
+            bool reset = (c.k == 0);
+            if (c.k > 0) {
+                if (fv > 0.0) {
+                    c.npos += 1;
+                    if (c.npos > m.nmin) {
+                        dt = fmin(dt * m.finc, m.dtmax);
+                        alpha *= m.falpha;
+                    }
+                } else {
+                    c.npos = 0;
+                    dt *= m.fdec;
+                    alpha = m.alpha0;
+                    reset = true;
+                }
+            }
+            if (reset) {
+                fv = 0.0;
+                vv = 0.0;
+            }
+            // |v + dt f| from the old velocity's reductions (no second pass)
+            const double vnorm = sqrt(vv + 2.0 * dt * fv + dt * dt * ff);
+            const double fnorm = sqrt(ff);
+            c.fire_dt = dt;
+            c.fire_alpha = alpha;
+            c.c_keep = reset ? 0.0 : 1.0;
+            c.mix_v = fnorm > 0.0 ? 1.0 - alpha : 1.0;
+            c.mix_f = fnorm > 0.0 ? alpha * (vnorm / fnorm) : 0.0;
+            c.updates += 1;
+        }
+        c.k += 1;
+        out[MXE_S_UPDATES] = (double)c.updates;
+        out[MXE_S_CONVERGED] = (double)c.converged;
+        out[MXE_S_EVALS] = (double)c.evals;
+    }
+    out[MXE_S_STATUS] = (double)c.status;
+}
+
+void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s) {
+    k_control<<<d.n_sys, kChunk, 0, s>>>(d, m, mode);
+}
+
+// FIRE velocity mixing and position/width update; flags a list rebuild when a
+// site leaves its skin budget and records the running largest width.
+__global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
+    __shared__ double lds[kChunk / kWave];
+    const Chunk ch = d.chunks[blockIdx.x];
+    SysCtl& c = d.ctl[ch.sys];
+    if (c.done) return;
+    const int i = ch.start + threadIdx.x;
+    const double dt = c.fire_dt, mv = c.mix_v, mf = c.mix_f;
+    const bool keep = c.c_keep != 0.0;
+    double sg_new = 0.0;
+    if (i < ch.end) {
+        const double f[4] = {d.fx[i], d.fy[i], d.fz[i], d.fs[i]};
+        double* v[4] = {d.vx + i, d.vy + i, d.vz + i, d.vs + i};
+        double* y[4] = {d.qx + i, d.qy + i, d.qz + i, d.sigma + i};
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const double vt = (keep ? *v[a] : 0.0) + dt * f[a];
+            const double vn = mv * vt + mf * f[a];
+            *v[a] = vn;
+            *y[a] += dt * vn;
+        }
+        sg_new = d.sigma[i];
+        if (sg_new < m.sigma_min) {
+            sg_new = m.sigma_min;
+            d.sigma[i] = sg_new;
+            atomicOr(&c.status, MXE_STAT_SIGMA_MIN);
+        }
+        if (sg_new > m.sigma_cap) atomicOr(&c.status, MXE_STAT_SIGMA_CAP);
+        const double dx = d.qx[i] - d.qrx[i], dy = d.qy[i] - d.qry[i], dz = d.qz[i] - d.qrz[i];
+        const double quarter = 0.25 * m.skin;
+        const bool moved = dx * dx + dy * dy + dz * dz > quarter * quarter;
+        const bool widened = 3.0 * sqrt(2.0) * (sg_new - d.sref[i]) > 0.5 * m.skin;
+        if (moved || widened) c.rebuild = 1;
+    }
+    const double mx = block_max(sg_new, lds);
+    if (threadIdx.x == 0)
+        atomicMax(&c.sigmax_bits, (unsigned long long)__double_as_longlong(mx));
+}
+
+void launch_update(const Dev& d, const Model& m, hipStream_t s) {
+    k_update<<<d.n_chunks, kChunk, 0, s>>>(d, m);
+}
+
+// ---------------------------------------------------------------------------
+// Master equation
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kChunk) void k_flux(Dev d, Model m) {
+    __shared__ double lds[kChunk / kWave];
+    const Chunk ch = d.chunks[blockIdx.x];
+    const SysDesc& S = d.sys[ch.sys];
+    const int i = ch.start + threadIdx.x;
+    double rate = 0.0;
+    if (i < ch.end) {
+        double acc = 0.0, rout = 0.0, rin = 0.0;
+        const int ti = d.type[i];
+        if (occ_mobile(ti)) {
+            const double D = S.D, cb = m.kin_c * S.beta;
+            const int nb = d.nbond[i];
+            const int* row = d.bond + (int64_t)i * d.bond_max;
+            for (int b = 0; b < nb; ++b) {
+                const int j = row[b];
+                const bool i_lo = i < j;
+                const int lo = i_lo ? i : j, hi = i_lo ? j : i;
+                const double xl = d.x[lo], xh = d.x[hi];
+                const double arg = cb * (d.mu[hi] - d.mu[lo]);
+                const double e_hl = exp(arg);   // rate factor of a hop hi -> lo
+                const double e_lh = exp(-arg);  // rate factor of a hop lo -> hi
+                // net flux from hi into lo
+                const double J = D * (xh * (1.0 - xl) * e_hl - xl * (1.0 - xh) * e_lh);
+                acc += i_lo ? J : -J;
+                const double xj = i_lo ? xh : xl;
+                rout += D * (1.0 - xj) * (i_lo ? e_lh : e_hl);
+                rin += D * xj * (i_lo ? e_hl : e_lh);
+            }
+        }
+        d.dxdt[i] = acc;
+        rate = fmax(rout, rin);
+    }
+    const double mx = block_max(rate, lds);
+    if (threadIdx.x == 0) d.part[(int64_t)blockIdx.x * kNPart + P_RATE] = mx;
+}
+
+__global__ __launch_bounds__(kChunk) void k_mstep_ctl(Dev d, Model m, double dt_in) {
+    __shared__ double lds[kChunk / kWave];
+    const int s = blockIdx.x;
+    const SysDesc& S = d.sys[s];
+    double r = 0.0;
+    for (int k = threadIdx.x; k < S.n_chunks; k += blockDim.x)
+        r = fmax(r, d.part[(int64_t)(S.chunk_first + k) * kNPart + P_RATE]);
+    r = block_max(r, lds);
+    if (threadIdx.x != 0) return;
+    const double dt = dt_in > 0.0 ? dt_in : (r > 0.0 ? m.dt_safety / r : 0.0);
+    d.ctl[s].dt_master = dt;
+    double* out = sc(d, s);
+    out[MXE_S_DT] = dt;
+    out[MXE_S_TIME] += dt;
+}
+
+__global__ __launch_bounds__(kChunk) void k_euler(Dev d) {
+    __shared__ double lds[kChunk / kWave];
+    const Chunk ch = d.chunks[blockIdx.x];
+    const int i = ch.start + threadIdx.x;
+    double xi = 0.0;
+    if (i < ch.end) {
+        xi = d.x[i];
+        if (occ_mobile(d.type[i])) {
+            xi += d.ctl[ch.sys].dt_master * d.dxdt[i];
+            d.x[i] = xi;
+            if (!(xi >= -1e-12 && xi <= 1.0 + 1e-12)) atomicOr(&d.ctl[ch.sys].status, MXE_STAT_X_RANGE);
+        }
+    }
+    const double t = block_sum(xi, lds);
+    if (threadIdx.x == 0) d.part[(int64_t)blockIdx.x * kNPart + P_SUMX] = t;
+}
+
+__global__ __launch_bounds__(kChunk) void k_estep_ctl(Dev d) {
+    __shared__ double lds[kChunk / kWave];
+    const int s = blockIdx.x;
+    const SysDesc& S = d.sys[s];
+    double t = 0.0;
+    for (int k = threadIdx.x; k < S.n_chunks; k += blockDim.x)
+        t += d.part[(int64_t)(S.chunk_first + k) * kNPart + P_SUMX];
+    t = block_sum(t, lds);
+    if (threadIdx.x != 0) return;
+    double* out = sc(d, s);
+    out[MXE_S_SUMX] = t;
+    out[MXE_S_STATUS] = (double)d.ctl[s].status;
+}
+
+void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s) {
+    k_flux<<<d.n_chunks, kChunk, 0, s>>>(d, m);
+    k_mstep_ctl<<<d.n_sys, kChunk, 0, s>>>(d, m, dt_in);
+    k_euler<<<d.n_chunks, kChunk, 0, s>>>(d);
+    k_estep_ctl<<<d.n_sys, kChunk, 0, s>>>(d);
+}
+
+}  // namespace mxe

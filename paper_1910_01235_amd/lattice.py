@@ -180,7 +180,8 @@ def nanowire(radius: float = 50.0, n_axial: int = 55, x_shell: float = 0.1, T: f
 def config3(seed: int = 3) -> Workload:
     """Interstitial solute in a host nanowire: R = 50 A, 55 cells along the axis, T = 600 K."""
     s = nanowire(name="c3_nanowire_265k")
-    p = dict(DEFAULT_PARAMS, max_relax=30, **PDH_KINETICS)
+    # host sites see ~54 host and ~68-86 octahedral neighbours inside the list radius
+    p = dict(DEFAULT_PARAMS, max_relax=30, k_max=160, **PDH_KINETICS)
     return Workload("c3_nanowire_265k", [s], params=p, n_steps=300, precision="fp32")
 
 

@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every entry point include/mxe.h declares.
+
+No compute call is made here (no GPU in this check)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "mxe.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mxe_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("mxe_plan_create", "mxe_evaluate", "mxe_relax", "mxe_step", "mxe_run",
+              "mxe_workspace_bytes", "mxe_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1910_01235_amd import mxe
+    if not os.path.exists(mxe.LIB_PATH):
+        pytest.skip("libmxe.so not built")
+    lib = ctypes.CDLL(mxe.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert sorted(mxe.EXPORTED) == declared_functions()
+
+
+def test_plan_validation_needs_no_gpu():
+    """Plan creation is host-only: argument checks and workspace sizing."""
+    from paper_1910_01235_amd import lattice as L
+    from paper_1910_01235_amd import mxe
+    if not os.path.exists(mxe.LIB_PATH):
+        pytest.skip("libmxe.so not built")
+    w = L.config0(0)
+    plan = mxe.Plan(w.systems, w.eam, w.params)
+    assert plan.n_sites == 256 and plan.ws_bytes > 0
+    # a periodic box shorter than twice the list radius is rejected
+    s = L.vacancy_bulk(3, 0, 800.0, 0)
+    with pytest.raises(mxe.MxeError, match="periodic box"):
+        mxe.Plan([s], w.eam, w.params)
+    # an empty system is rejected
+    e = s.copy()
+    e.q = e.q[:0]
+    with pytest.raises(mxe.MxeError, match="n_sites"):
+        mxe.Plan([e], w.eam, w.params)
+    with pytest.raises(mxe.MxeError, match="symmetric"):
+        bad = dict(w.eam, pair_a=[[0.3, 0.1, 0.2], [0.2, 0.36, 0.2], [0.2, 0.2, 0.0]])
+        mxe.Plan(w.systems, bad, w.params)
+    # fp32 workspace is smaller (FP32 moments)
+    p32 = mxe.Plan(w.systems, w.eam, w.params, precision="fp32")
+    assert p32.ws_bytes < plan.ws_bytes
