@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=24576)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph and FP32 legs")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with a 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -185,6 +187,14 @@ def main():
                                     kernel_ms={k: v[0] for k, v in prof32.items()})
         log(f"fp32 leg: {wall_32:.3f} s")
 
+    if args.calib_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = a.numel() * 8
     if not args.no_cpu_baseline:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

@@ -40,10 +40,10 @@ struct mxe_plan {
     std::vector<Chunk> chunks, pchunks;
     int64_t n_sites = 0, n_cells = 0, pair_cap_total = 0;
     // workspace layout (byte offsets)
-    size_t o_sys, o_ctl, o_chunks, o_pchunks, o_site_sys, o_cell_count, o_cell_start, o_cell_sites;
+    size_t o_sys, o_ctl, o_chunks, o_pchunks, o_site_sys, o_cell_count, o_cell_start, o_cell_sites, o_cell_rec;
     size_t o_cell_of, o_slot_of, o_chunk_up, o_chunk_off;
     size_t o_nbr, o_cnt, o_lo, o_pid, o_hoff, o_pi, o_pj, o_fblk, o_dblk, o_G, o_A, o_B;
-    size_t o_v, o_qr, o_sref, o_bond, o_nbond, o_part;
+    size_t o_v, o_qr, o_sref, o_emit, o_srec, o_bond, o_nbond, o_part;
     size_t ws_bytes = 0;
     // graph cache for mxe_run
     hipStream_t cap_stream = nullptr;
@@ -201,6 +201,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     P->n_cells = cell_off;
     P->pair_cap_total = pair_base;
     if (site_off * (int64_t)p.k_max >= (int64_t)INT32_MAX || pair_base >= (int64_t)INT32_MAX ||
+        site_off * 4 >= (int64_t)INT32_MAX ||
         cell_off >= (int64_t)INT32_MAX) {
         delete P;
         return fail(MXE_ERANGE, "plan too large for 32-bit indices");
@@ -224,6 +225,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     P->o_cell_count = take(sizeof(int) * P->n_cells);
     P->o_cell_start = take(sizeof(int) * P->n_cells);
     P->o_cell_sites = take(sizeof(int) * N);
+    P->o_cell_rec = take(sizeof(double) * 4 * N);
     P->o_cell_of = take(sizeof(int) * N);
     P->o_slot_of = take(sizeof(int) * N);
     P->o_chunk_up = take(sizeof(int) * P->chunks.size());
@@ -243,6 +245,8 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     P->o_v = take(sizeof(double) * 4 * N);
     P->o_qr = take(sizeof(double) * 3 * N);
     P->o_sref = take(sizeof(double) * N);
+    P->o_emit = take(sizeof(double) * N);
+    P->o_srec = take(sizeof(double) * kSRec * N);
     P->o_bond = take(sizeof(int) * N * p.bond_max);
     P->o_nbond = take(sizeof(int) * N);
     P->o_part = take(sizeof(double) * kNPart * P->chunks.size());
@@ -309,6 +313,7 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.cell_count = (int*)(w + P->o_cell_count);
     D.cell_start = (int*)(w + P->o_cell_start);
     D.cell_sites = (int*)(w + P->o_cell_sites);
+    D.cell_rec = (double4*)(w + P->o_cell_rec);
     D.cell_of = (int*)(w + P->o_cell_of);
     D.slot_of = (int*)(w + P->o_slot_of);
     D.chunk_up = (int*)(w + P->o_chunk_up);
@@ -335,6 +340,8 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.qry = qr + N;
     D.qrz = qr + 2 * N;
     D.sref = (double*)(w + P->o_sref);
+    D.emit = (double*)(w + P->o_emit);
+    D.srec = (double*)(w + P->o_srec);
     D.bond = (int*)(w + P->o_bond);
     D.nbond = (int*)(w + P->o_nbond);
     D.part = (double*)(w + P->o_part);

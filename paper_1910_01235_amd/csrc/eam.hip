@@ -12,10 +12,10 @@
 //              shapes share each node's distance. Stored per pair as one force
 //              block (16 slots: a 128-byte line in FP64) and one density pair
 //              (<f>, f0), so a gather from either end reads whole lines.
-//   k_density  one wavefront per site, lanes over its neighbour row: gathers
+//   k_density  kLPS lanes per site, lanes over its neighbour row: gathers
 //              rho_bar = sum_j b_j <f>, rho0 = sum_j b_j f0 (Eq. EAM-density-
 //              substitutional-ave), then the Taylor embedding terms.
-//   k_force    one wavefront per site: gathers the moments with the sign of the
+//   k_force    kLPS lanes per site: gathers the moments with the sign of the
 //              pair's direction and the neighbours' embedding terms, giving the
 //              exact gradient of the free energy, mu and the site's energy share,
 //              plus the chunk partial sums that drive FIRE.
@@ -27,17 +27,95 @@ namespace mxe {
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// Node arithmetic. The arguments are bounded by the pair geometry: distances
+// lie in (0, r_c), so exp sees arguments of modest size and the taper argument
+// lies in [0, 1]. The FP64 routines below exploit that (no special cases):
+//  * exp: Cody-Waite reduction x = n ln2 + r, |r| <= ln2/2 (ln2 split in a
+//    32-bit head and a tail so n * head is exact), e^r by its Taylor series to
+//    degree 12 (truncation < 2.3e-16 relative), then scaling by 2^n.
+//  * 1/sqrt: the hardware reciprocal square root refined by two Newton steps.
+//  * taper: with v = t - 1/2 and z = pi v (|z| <= pi/2), cos(pi t) = -sin z and
+//    sin(pi t) = cos z, from their Taylor series to degrees 21 and 20.
+// The FP32 variant uses the hardware exp2, rsq and sin/cos instructions.
+// ---------------------------------------------------------------------------
+__device__ inline double exp_bounded(double x) {
+    constexpr double kLog2e = 1.4426950408889634;
+    constexpr double kLn2Hi = 0.6931471803691238;      // 32 significant bits
+    constexpr double kLn2Lo = 1.9082149292705877e-10;  // ln 2 - kLn2Hi
+    const double n = rint(x * kLog2e);
+    const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, x));
+    double p = 2.08767569878681e-09;  // 1/12!
+    p = fma(p, r, 2.505210838544172e-08);
+    p = fma(p, r, 2.755731922398589e-07);
+    p = fma(p, r, 2.7557319223985893e-06);
+    p = fma(p, r, 2.48015873015873e-05);
+    p = fma(p, r, 0.0001984126984126984);
+    p = fma(p, r, 0.001388888888888889);
+    p = fma(p, r, 0.008333333333333333);
+    p = fma(p, r, 0.041666666666666664);
+    p = fma(p, r, 0.16666666666666666);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
+__device__ inline double rsqrt_refined(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// S(t) = (1 + cos(pi t)) / 2 and sin(pi t) for t in [0, 1]
+__device__ inline void taper_terms(double t, double& S, double& sn) {
+    constexpr double kPi = 3.141592653589793;
+    const double z = kPi * (t - 0.5);
+    const double z2 = z * z;
+    double ps = -1.9572941063391263e-20;  // sin z: z - z^3/3! + ... - z^21/21! (odd terms)
+    ps = fma(ps, z2, 8.22063524662433e-18);
+    ps = fma(ps, z2, -2.8114572543455206e-15);
+    ps = fma(ps, z2, 7.647163731819816e-13);
+    ps = fma(ps, z2, -1.6059043836821613e-10);
+    ps = fma(ps, z2, 2.505210838544172e-08);
+    ps = fma(ps, z2, -2.7557319223985893e-06);
+    ps = fma(ps, z2, 0.0001984126984126984);
+    ps = fma(ps, z2, -0.008333333333333333);
+    ps = fma(ps, z2, 0.16666666666666666);
+    ps = fma(-ps, z2, 1.0);
+    const double sinz = ps * z;
+    double pc = 4.110317623312165e-19;  // cos z: 1 - z^2/2! + ... + z^20/20!
+    pc = fma(pc, z2, -1.5619206968586225e-16);
+    pc = fma(pc, z2, 4.779477332387385e-14);
+    pc = fma(pc, z2, -1.1470745597729725e-11);
+    pc = fma(pc, z2, 2.08767569878681e-09);
+    pc = fma(pc, z2, -2.755731922398589e-07);
+    pc = fma(pc, z2, 2.48015873015873e-05);
+    pc = fma(pc, z2, -0.001388888888888889);
+    pc = fma(pc, z2, 0.041666666666666664);
+    pc = fma(pc, z2, -0.5);
+    pc = fma(pc, z2, 1.0);
+    S = 0.5 * (1.0 - sinz);
+    sn = pc;
+}
+
 template <typename T> struct Math;
 
 template <> struct Math<double> {
-    static __device__ inline double ex(double v) { return exp(v); }
-    static __device__ inline double sq(double v) { return sqrt(v); }
-    static __device__ inline void scpi(double t, double* s, double* c) { sincospi(t, s, c); }
+    static __device__ inline double ex(double v) { return exp_bounded(v); }
+    static __device__ inline double rsq(double v) { return rsqrt_refined(v); }
+    static __device__ inline void taper(double t, double& S, double& sn) { taper_terms(t, S, sn); }
 };
 template <> struct Math<float> {
     static __device__ inline float ex(float v) { return __expf(v); }
-    static __device__ inline float sq(float v) { return __fsqrt_rn(v); }
-    static __device__ inline void scpi(float t, float* s, float* c) { sincospif(t, s, c); }
+    static __device__ inline float rsq(float v) { return __frsqrt_rn(v); }
+    static __device__ inline void taper(float t, float& S, float& sn) {
+        float c;
+        sincospif(t, &sn, &c);
+        S = 0.5f * (1.0f + c);
+    }
 };
 
 // Radial shapes of both pair functions at distance r (r < r_c):
@@ -49,9 +127,8 @@ __device__ inline void shapes(T r, T inv_re, T al, T ga, T r_s, T tw, T& gp, T& 
     const T ef = Math<T>::ex(-ga * u);
     T S = T(1), dS = T(0);
     if (r > r_s) {
-        T sn, cs;
-        Math<T>::scpi((r - r_s) * tw, &sn, &cs);
-        S = T(0.5) * (T(1) + cs);
+        T sn;
+        Math<T>::taper((r - r_s) * tw, S, sn);
         dS = T(-0.5) * T(3.14159265358979323846) * tw * sn;
     }
     gp = ep * S;
@@ -86,8 +163,8 @@ __device__ inline void pair_moments(const Model& m, int cls, double rx, double r
                 const T r2 = X2[a] + Y2[b] + Z2[c];
                 if (r2 < rc2 && r2 > T(0)) {
                     const T W = w1[a] * w1[b] * w1[c];
-                    const T r = Math<T>::sq(r2);
-                    const T rinv = T(1) / r;
+                    const T rinv = Math<T>::rsq(r2);
+                    const T r = r2 * rinv;
                     T gp, dgp, gf, dgf;
                     shapes<T>(r, inv_re, al, ga, r_s, tw, gp, dgp, gf, dgf);
                     // node offset zeta = sqrt(3) (a-1, b-1, c-1); d . zeta
@@ -139,7 +216,7 @@ struct alignas(16) Vec16 {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_pair(Dev d, Model m) {
+__global__ __launch_bounds__(256, 3) void k_pair(Dev d, Model m) {
     const Chunk ch = d.pchunks[blockIdx.x];
     const SysCtl& c = d.ctl[ch.sys];
     if (c.done) return;
@@ -172,27 +249,42 @@ __global__ __launch_bounds__(256) void k_pair(Dev d, Model m) {
     }
 }
 
+// Gathers run LPS lanes per site, so one wavefront serves 64 / LPS sites at a
+// time and keeps that many sites' loads in flight.
+constexpr int kLPS = 16;
+constexpr int kGroups = kChunk / kLPS;  // concurrent sites per block
+
+template <int LPS>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+    for (int o = LPS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
     const Chunk ch = d.chunks[blockIdx.x];
     if (d.ctl[ch.sys].done) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
     const T* dblk = (const T*)d.dblk;
     const int K = d.K;
-    for (int i = ch.start + wave; i < ch.end; i += kChunk / kWave) {
+    for (int i = ch.start + grp; i < ch.end; i += kGroups) {
         const int cnt = d.nbr_cnt[i];
+        const int* row = d.nbr + (int64_t)i * K;
+        const int* prow = d.pid + (int64_t)i * K;
         double rb = 0.0, r0 = 0.0;
-        for (int k = lane; k < cnt; k += kWave) {
-            const int j = d.nbr[(int64_t)i * K + k];
-            const int p = d.pid[(int64_t)i * K + k];
+#pragma unroll 2
+        for (int k = sub; k < cnt; k += kLPS) {
+            const int j = row[k];
+            const int p = prow[k];
             if (p < 0) continue;
-            const double bj = mixval(m.b4, d.type[j], d.x[j]);
+            const double bj = d.emit[j];
             rb += bj * (double)dblk[2 * (int64_t)p];
             r0 += bj * (double)dblk[2 * (int64_t)p + 1];
         }
-        rb = wave_sum(rb);
-        r0 = wave_sum(r0);
-        if (lane == 0) {
+        rb = group_sum<kLPS>(rb);
+        r0 = group_sum<kLPS>(r0);
+        if (sub == 0) {
             const int ti = d.type[i];
             const double xi = d.x[i];
             d.rho_bar[i] = rb;
@@ -215,6 +307,18 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
             d.G[i] = G;
             d.Ahat[i] = A;
             d.Bhat[i] = B;
+            // record read by the force gather of the neighbours: A~ = w A^, B~ = w B^,
+            // the emission and the pair amplitude against a partner of species A, B, S
+            const double w = occ_partial(ti) ? xi : 1.0;
+            const double p1 = occ_p1(ti, xi);
+            const int s1 = occ_sp1(ti), s0 = occ_sp0(ti);
+            double* R = d.srec + (int64_t)i * kSRec;
+            R[0] = w * A;
+            R[1] = w * B;
+            R[2] = d.emit[i];
+            for (int k = 0; k < 3; ++k) R[3 + k] = p1 * m.a4[k][s1] + (1.0 - p1) * m.a4[k][s0];
+            R[6] = 0.0;
+            R[7] = 0.0;
         }
     }
 }
@@ -229,22 +333,29 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
 //                       + 3 kT / sigma_i
 //   mu_i = sum_j da_ij/dx_i <phi> + db_i/dx_i sum_j (A_j <f> + B_j f0)
 //          + dc_i/dx_i G_i - 3 kT dw_i/dx_i ln sigma_i
+// Force gather layout: kLPS lanes per site; inside them, groups of four lanes
+// share one row entry, each lane loading a quarter of the pair's force block
+// (slots 4q .. 4q+3) and the neighbour's record. A wave-wide block load then
+// touches one cache line per entry instead of one per lane.
+constexpr int kQ = 4;
+
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
-    __shared__ double red[kChunk / kWave][6];
+    __shared__ double red[kGroups][6];
     const Chunk ch = d.chunks[blockIdx.x];
     const int sys = ch.sys;
     if (d.ctl[sys].done) return;
     const SysDesc& S = d.sys[sys];
     const double kT = S.kT;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
+    const int q = sub % kQ, es = sub / kQ;  // quarter of the block; entry slot
     const Vec16<T>* fblk = (const Vec16<T>*)d.fblk;
-    constexpr int per = kFBlk / Vec16<T>::n;
+    constexpr int per = kFBlk / Vec16<T>::n;  // vectors per block
+    constexpr int perq = per / kQ;            // vectors per quarter
     const int K = d.K;
-    // running chunk partials, held by lane 0 of each wave
     double pe = 0.0, pfmax = 0.0, pfv = 0.0, pff = 0.0, pvv = 0.0, psx = 0.0;
     int bad = 0;
-    for (int i = ch.start + wave; i < ch.end; i += kChunk / kWave) {
+    for (int i = ch.start + grp; i < ch.end; i += kGroups) {
         const int ti = d.type[i];
         const double xi = d.x[i], si = d.sigma[i];
         const double Ahi = d.Ahat[i], Bhi = d.Bhat[i];
@@ -253,50 +364,64 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
         const double bhat_i = mixhat(m.b4, ti, xi), db_i = mixdx(m.b4, ti);
         const bool part_i = occ_partial(ti), mob_i = occ_mobile(ti);
         const int cnt = d.nbr_cnt[i];
+        const int* row = d.nbr + (int64_t)i * K;
+        const int* prow = d.pid + (int64_t)i * K;
         double fx = 0.0, fy = 0.0, fz = 0.0, fsg = 0.0, mu = 0.0, ep = 0.0;
-        for (int k = lane; k < cnt; k += kWave) {
-            const int j = d.nbr[(int64_t)i * K + k];
-            const int p = d.pid[(int64_t)i * K + k];
+        for (int k = es; k < cnt; k += kLPS / kQ) {
+            const int j = row[k];
+            const int p = prow[k];
             if (p < 0) continue;
-            const int tj = d.type[j];
-            const double xj = d.x[j];
-            const double pj1 = occ_p1(tj, xj);
-            const int j1 = occ_sp1(tj), j0 = occ_sp0(tj);
-            const double a1 = pj1 * m.a4[i1][j1] + (1.0 - pj1) * m.a4[i1][j0];
-            const double a0 = pj1 * m.a4[i0][j1] + (1.0 - pj1) * m.a4[i0][j0];
+            T mq[4];
+#pragma unroll
+            for (int v = 0; v < perq; ++v) {
+                const Vec16<T> b = fblk[(int64_t)p * per + q * perq + v];
+#pragma unroll
+                for (int e = 0; e < Vec16<T>::n; ++e) mq[v * Vec16<T>::n + e] = b.v[e];
+            }
+            const double2* R = (const double2*)(d.srec + (int64_t)j * kSRec);
+            const double2 r01 = R[0], r23 = R[1], r45 = R[2];
+            const double Aj = r01.x, Bj = r01.y, bj = r23.x;
+            const double ampA[3] = {r23.y, r45.x, r45.y};
+            const double a1 = ampA[i1];
+            const double a0 = i0 < 3 ? ampA[i0] : 0.0;
             const double aij = pi1 * a1 + (1.0 - pi1) * a0;
             const double ahat = part_i ? a1 : aij;
             const double dadx = mob_i ? a1 - a0 : 0.0;
-            const double wj = occ_partial(tj) ? xj : 1.0;
-            const double Aj = wj * d.Ahat[j], Bj = wj * d.Bhat[j];
-            const double bj = mixval(m.b4, tj, xj);
             const double hA = Ahi * bj + Aj * bhat_i;
             const double hB = Bhi * bj + Bj * bhat_i;
             const double sg = j > i ? 1.0 : -1.0;
-            T mb[kFBlk];
-#pragma unroll
-            for (int v = 0; v < per; ++v) {
-                const Vec16<T> b = fblk[(int64_t)p * per + v];
-#pragma unroll
-                for (int e = 0; e < Vec16<T>::n; ++e) mb[v * Vec16<T>::n + e] = b.v[e];
+            const double m0 = (double)mq[0], m1 = (double)mq[1], m2 = (double)mq[2], m3 = (double)mq[3];
+            if (q == 0) {         // <phi>, grad <phi>
+                ep += aij * m0;
+                mu += dadx * m0;
+                const double c = sg * ahat;
+                fx += c * m1;
+                fy += c * m2;
+                fz += c * m3;
+            } else if (q == 1) {  // <phi>_s / s, <f>, grad <f> (x, y)
+                fsg += ahat * m0;
+                mu += db_i * Aj * m1;
+                const double c = sg * hA;
+                fx += c * m2;
+                fy += c * m3;
+            } else if (q == 2) {  // grad <f> (z), <f>_s / s, f0, grad f0 (x)
+                fz += sg * hA * m0;
+                fsg += hA * m1;
+                mu += db_i * Bj * m2;
+                fx += sg * hB * m3;
+            } else {              // grad f0 (y, z)
+                const double c = sg * hB;
+                fy += c * m0;
+                fz += c * m1;
             }
-            const double mphi = (double)mb[M_PHI];
-            const double mf = (double)mb[M_F];
-            const double mf0 = (double)mb[M_F0];
-            fx += sg * (ahat * (double)mb[M_GPHI + 0] + hA * (double)mb[M_GF + 0] + hB * (double)mb[M_GF0 + 0]);
-            fy += sg * (ahat * (double)mb[M_GPHI + 1] + hA * (double)mb[M_GF + 1] + hB * (double)mb[M_GF0 + 1]);
-            fz += sg * (ahat * (double)mb[M_GPHI + 2] + hA * (double)mb[M_GF + 2] + hB * (double)mb[M_GF0 + 2]);
-            fsg += ahat * (double)mb[M_SPHI] + hA * (double)mb[M_SF];
-            mu += dadx * mphi + db_i * (Aj * mf + Bj * mf0);
-            ep += aij * mphi;
         }
-        fx = wave_sum(fx);
-        fy = wave_sum(fy);
-        fz = wave_sum(fz);
-        fsg = wave_sum(fsg);
-        mu = wave_sum(mu);
-        ep = wave_sum(ep);
-        if (lane == 0) {
+        fx = group_sum<kLPS>(fx);
+        fy = group_sum<kLPS>(fy);
+        fz = group_sum<kLPS>(fz);
+        fsg = group_sum<kLPS>(fsg);
+        mu = group_sum<kLPS>(mu);
+        ep = group_sum<kLPS>(ep);
+        if (sub == 0) {
             const double Gi = d.G[i];
             const double lns = log(si);
             const double fs = -si * fsg + 3.0 * kT / si;
@@ -325,26 +450,26 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
             if (!isfinite(fx + fy + fz + fs + ei + mui)) bad = 1;
         }
     }
-    if (lane == 0) {
-        red[wave][0] = pe;
-        red[wave][1] = pfmax;
-        red[wave][2] = pfv;
-        red[wave][3] = pff;
-        red[wave][4] = pvv;
-        red[wave][5] = psx;
+    if (sub == 0) {
+        red[grp][0] = pe;
+        red[grp][1] = pfmax;
+        red[grp][2] = pfv;
+        red[grp][3] = pff;
+        red[grp][4] = pvv;
+        red[grp][5] = psx;
         if (bad) atomicOr(&d.ctl[sys].status, MXE_STAT_NONFINITE);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double* P = d.part + (int64_t)blockIdx.x * kNPart;
         double e = red[0][0], fm = red[0][1], fv = red[0][2], ff = red[0][3], vv = red[0][4], sx = red[0][5];
-        for (int w = 1; w < kChunk / kWave; ++w) {
-            e += red[w][0];
-            fm = fmax(fm, red[w][1]);
-            fv += red[w][2];
-            ff += red[w][3];
-            vv += red[w][4];
-            sx += red[w][5];
+        for (int g = 1; g < kGroups; ++g) {
+            e += red[g][0];
+            fm = fmax(fm, red[g][1]);
+            fv += red[g][2];
+            ff += red[g][3];
+            vv += red[g][4];
+            sx += red[g][5];
         }
         P[P_E] = e;
         P[P_FMAX] = fm;

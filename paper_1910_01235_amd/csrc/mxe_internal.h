@@ -10,6 +10,7 @@ namespace mxe {
 
 constexpr int kMom = 14;            // moments computed per pair (see pair kernel)
 constexpr int kFBlk = 16;           // force block per pair: 14 moments + 2 pad = one 128-byte line (FP64)
+constexpr int kSRec = 8;            // per-site record: A~, B~, b, pair amplitude against A, B, S, 2 pad
 constexpr int kChunk = 256;         // sites per site-chunk; block size of per-site kernels
 constexpr int kPairChunk = 4096;    // pair slots per pair-chunk
 constexpr int kNPart = 8;           // partial sums per site-chunk
@@ -85,7 +86,8 @@ struct Dev {
     int* site_sys;
     int* cell_count;   // sites per cell (zero between builds)
     int* cell_start;   // first entry of each cell in cell_sites
-    int* cell_sites;   // site indices grouped by cell, N entries
+    int* cell_sites;   // 4 * site index + site type, grouped by cell, N entries
+    double4* cell_rec; // (qx, qy, qz, sigma) of the same entries
     int *cell_of, *slot_of;
     int *chunk_up, *chunk_off;
     int *nbr, *nbr_cnt, *nbr_lo, *pid, *half_off;
@@ -93,6 +95,8 @@ struct Dev {
     void* fblk;   // [pair][kFBlk] force blocks (T)
     void* dblk;   // [pair][2] density pair (<f>, f0) (T)
     double *G, *Ahat, *Bhat;
+    double* emit;  // density emitted by each site, b_i (refreshed when x changes)
+    double* srec;  // per-site record read by the force gather, kSRec doubles per site
     double *vx, *vy, *vz, *vs;
     double *qrx, *qry, *qrz, *sref;
     int *bond, *nbond;

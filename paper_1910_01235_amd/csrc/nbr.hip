@@ -13,8 +13,8 @@
 // Build chain per system (each kernel skips systems whose rebuild flag is 0):
 //   k_bin        cell of each site and its slot in the cell (atomic count)
 //   k_cell_scan  per system: cell offsets (exclusive scan of the counts)
-//   k_fill       place each site in its cell
-//   k_sort_cells sort each cell by site index (deterministic order)
+//   k_fill       place each site in its cell (order within a cell is not
+//                deterministic; rows are sorted afterwards, so nothing depends on it)
 //   k_nbr        one wavefront per site: lanes test the stencil's candidates,
 //                survivors are compacted by ballot and sorted (bitonic, in LDS);
 //                per-chunk count of "upper" neighbours (larger index)
@@ -120,6 +120,7 @@ __global__ __launch_bounds__(kChunk) void k_site_init(Dev d, Model m) {
         if (!isfinite(xi) || xi < -1e-12 || xi > 1.0 + 1e-12) st |= MXE_STAT_X_RANGE;
         if (!isfinite(d.qx[i]) || !isfinite(d.qy[i]) || !isfinite(d.qz[i])) st |= MXE_STAT_NONFINITE;
         if (!(sg > 0.0)) sg = 0.0;
+        d.emit[i] = mixval(m.b4, d.type[i], xi);
     }
     if (st) atomicOr(&d.ctl[ch.sys].status, st);
     double v = sg;
@@ -149,20 +150,6 @@ __device__ inline int64_t site_cell(const SysDesc& S, double q0, double q1, doub
     const int cy = cell_coord(q1, S.box[1], S.cell_w[1], S.nc[1], S.periodic[1]);
     const int cz = cell_coord(q2, S.box[2], S.cell_w[2], S.nc[2], S.periodic[2]);
     return S.cell_off + ((int64_t)cx * S.nc[1] + cy) * S.nc[2] + cz;
-}
-
-// the up-to-27 distinct cells around site position q (stencil order)
-__device__ inline int stencil_cells(const SysDesc& S, double q0, double q1, double q2, int64_t cells[27]) {
-    int cx[3], cy[3], cz[3];
-    const int nx = stencil_axis(cell_coord(q0, S.box[0], S.cell_w[0], S.nc[0], S.periodic[0]), S.nc[0], S.periodic[0], cx);
-    const int ny = stencil_axis(cell_coord(q1, S.box[1], S.cell_w[1], S.nc[1], S.periodic[1]), S.nc[1], S.periodic[1], cy);
-    const int nz = stencil_axis(cell_coord(q2, S.box[2], S.cell_w[2], S.nc[2], S.periodic[2]), S.nc[2], S.periodic[2], cz);
-    int n = 0;
-    for (int a = 0; a < nx; ++a)
-        for (int b = 0; b < ny; ++b)
-            for (int c = 0; c < nz; ++c)
-                cells[n++] = S.cell_off + ((int64_t)cx[a] * S.nc[1] + cy[b]) * S.nc[2] + cz[c];
-    return n;
 }
 
 // fixed-order exclusive scan over a 1024-thread block, one value per thread
@@ -219,38 +206,47 @@ __global__ __launch_bounds__(1024) void k_cell_scan(Dev d) {
     }
 }
 
+// Places each site in its cell and copies its position, width and type into
+// the cell-ordered records, so candidates of one cell are contiguous in memory.
 __global__ __launch_bounds__(kChunk) void k_fill(Dev d) {
     const Chunk ch = d.chunks[blockIdx.x];
     if (!d.ctl[ch.sys].rebuild) return;
     const int i = ch.start + threadIdx.x;
     if (i >= ch.end) return;
-    d.cell_sites[d.cell_start[d.cell_of[i]] + d.slot_of[i]] = i;
+    const int pos = d.cell_start[d.cell_of[i]] + d.slot_of[i];
+    d.cell_sites[pos] = i * 4 + d.type[i];
+    d.cell_rec[pos] = make_double4(d.qx[i], d.qy[i], d.qz[i], d.sigma[i]);
 }
 
-__global__ void k_sort_cells(Dev d) {
-    for (int64_t cell = gtid(); cell < d.n_cells; cell += gstride()) {
-        const int s = find_sys_cell(d.sys, d.n_sys, cell);
-        if (!d.ctl[s].rebuild) continue;
-        const int n = d.cell_count[cell];
-        int* c = d.cell_sites + d.cell_start[cell];
-        for (int a = 1; a < n; ++a) {
-            const int v = c[a];
-            int b = a - 1;
-            while (b >= 0 && c[b] > v) {
-                c[b + 1] = c[b];
-                --b;
-            }
-            c[b + 1] = v;
+// Cell of stencil offset (lane / 9 - 1, lane / 3 % 3 - 1, lane % 3 - 1) around the
+// cell (c0, c1, c2), or -1 if it falls outside an open axis or repeats a cell an
+// earlier offset already covers (periodic axes with fewer than three cells).
+__device__ inline int64_t stencil_lane_cell(const SysDesc& S, const int c[3], int lane) {
+    const int o[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
+    int v[3];
+    for (int a = 0; a < 3; ++a) {
+        const int nc = S.nc[a];
+        int w = c[a] + o[a];
+        if (S.periodic[a]) {
+            w = (w + nc) % nc;
+            // keep the first offset (in the order -1, 0, +1) that reaches w
+            for (int p = -1; p < o[a]; ++p)
+                if ((c[a] + p + nc) % nc == w) return -1;
+        } else if (w < 0 || w >= nc) {
+            return -1;
         }
+        v[a] = w;
     }
+    return S.cell_off + ((int64_t)v[0] * S.nc[1] + v[1]) * S.nc[2] + v[2];
 }
 
-// One wavefront per site. The wave walks the stencil's candidates as one flat
-// list (lane-strided), keeps those within the pair's list radius, compacts
-// them into an LDS row by ballot, then sorts the row by site index.
+// One wavefront per site. Lanes 0-26 each take one stencil cell; a wave scan
+// of the cell counts turns the stencil into one flat candidate list that the
+// lanes walk in strides of 64. Candidates within the pair's list radius are
+// compacted by ballot into an LDS row, which is then sorted (bitonic).
 __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int K2) {
     extern __shared__ int lds_rows[];  // kChunk / kWave rows of K2 entries
-    __shared__ int cstart[kChunk / kWave][28], cpre[kChunk / kWave][28];
+    __shared__ int cstart[kChunk / kWave][32], cpre[kChunk / kWave][33];
     __shared__ int wave_up[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
     const int s = ch.sys;
@@ -266,41 +262,71 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int K2) {
         const double qi0 = d.qx[i], qi1 = d.qy[i], qi2 = d.qz[i];
         const double si2 = d.sigma[i] * d.sigma[i];
         const int ti = d.type[i];
-        int64_t cells[27];
-        const int nc = stencil_cells(S, qi0, qi1, qi2, cells);
-        if (lane == 0) {
-            int acc = 0;
-            for (int c = 0; c < nc; ++c) {
-                cstart[wave][c] = d.cell_start[cells[c]];
-                cpre[wave][c] = acc;
-                acc += d.cell_count[cells[c]];
+        const int c[3] = {cell_coord(qi0, S.box[0], S.cell_w[0], S.nc[0], S.periodic[0]),
+                          cell_coord(qi1, S.box[1], S.cell_w[1], S.nc[1], S.periodic[1]),
+                          cell_coord(qi2, S.box[2], S.cell_w[2], S.nc[2], S.periodic[2])};
+        int cnt_c = 0, start_c = 0;
+        if (lane < 27) {
+            const int64_t cell = stencil_lane_cell(S, c, lane);
+            if (cell >= 0) {
+                cnt_c = d.cell_count[cell];
+                start_c = d.cell_start[cell];
             }
-            cpre[wave][nc] = acc;
         }
+        // inclusive wave scan of the counts (lanes >= 27 hold zero)
+        int incl = cnt_c;
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+            const int u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane < 32) {
+            cstart[wave][lane] = start_c;
+            cpre[wave][lane + 1] = incl;
+        }
+        if (lane == 0) cpre[wave][0] = 0;
+        const int total = __shfl(incl, 31);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        const int total = cpre[wave][nc];
         int n = 0;
-        for (int base = 0; base < total; base += kWave) {
-            const int e = base + lane;
-            bool ok = false;
-            int j = 0;
-            if (e < total) {
-                int c = 0;
-                while (cpre[wave][c + 1] <= e) ++c;
-                j = d.cell_sites[cstart[wave][c] + (e - cpre[wave][c])];
-                if (j != i && pair_cls(ti, d.type[j]) >= 0) {
-                    double dx = d.qx[j] - qi0, dy = d.qy[j] - qi1, dz = d.qz[j] - qi2;
-                    min_image(S, dx, dy, dz);
-                    const double sj = d.sigma[j];
-                    const double rl = reach + 3.0 * sqrt(si2 + sj * sj);
-                    ok = dx * dx + dy * dy + dz * dz < rl * rl;
+        // each lane takes kCand candidates per pass (independent load chains)
+        constexpr int kCand = 4;
+        for (int base = 0; base < total; base += kWave * kCand) {
+            int jc[kCand];
+            bool okc[kCand];
+#pragma unroll
+            for (int u = 0; u < kCand; ++u) {
+                const int e = base + u * kWave + lane;
+                jc[u] = -1;
+                bool ok = false;
+                if (e < total) {
+                    // cell holding flat index e: the last with cpre <= e (cells may be empty)
+                    int lo = 0, hi = 31;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (cpre[wave][mid] <= e) lo = mid; else hi = mid - 1;
+                    }
+                    const int pos = cstart[wave][lo] + (e - cpre[wave][lo]);
+                    const int jt = d.cell_sites[pos];
+                    const int j = jt >> 2;
+                    jc[u] = j;
+                    if (j != i && pair_cls(ti, jt & 3) >= 0) {
+                        const double4 rj = d.cell_rec[pos];
+                        double dx = rj.x - qi0, dy = rj.y - qi1, dz = rj.z - qi2;
+                        min_image(S, dx, dy, dz);
+                        const double rl = reach + 3.0 * sqrt(si2 + rj.w * rj.w);
+                        ok = dx * dx + dy * dy + dz * dz < rl * rl;
+                    }
                 }
+                okc[u] = ok;
             }
-            const unsigned long long mask = __ballot(ok);
-            const int pos = n + __popcll(mask & __lanemask_lt());
-            if (ok && pos < K2) row[pos] = j;
-            n += __popcll(mask);
+#pragma unroll
+            for (int u = 0; u < kCand; ++u) {
+                const unsigned long long mask = __ballot(okc[u]);
+                const int pos = n + __popcll(mask & __lanemask_lt());
+                if (okc[u] && pos < K2) row[pos] = jc[u];
+                n += __popcll(mask);
+            }
         }
         if (n > K) over = true;
         const int nk = min(n, K);
@@ -332,7 +358,8 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int K2) {
             out[k] = j;
             lo += (j < i);
         }
-        lo = (int)wave_sum((double)lo);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) lo += __shfl_xor(lo, o);
         if (lane == 0) {
             d.nbr_cnt[i] = nk;
             d.nbr_lo[i] = lo;
@@ -367,15 +394,20 @@ __global__ __launch_bounds__(kChunk) void k_bonds(Dev d, Model m) {
     if (occ_mobile(ti)) {
         const double rb2 = m.r_bond * m.r_bond;
         const double qi0 = d.qx[i], qi1 = d.qy[i], qi2 = d.qz[i];
-        int64_t cells[27];
-        const int nc = stencil_cells(S, qi0, qi1, qi2, cells);
-        for (int c = 0; c < nc; ++c) {
-            const int cn = d.cell_count[cells[c]];
-            const int* cs = d.cell_sites + d.cell_start[cells[c]];
+        const int cc[3] = {cell_coord(qi0, S.box[0], S.cell_w[0], S.nc[0], S.periodic[0]),
+                           cell_coord(qi1, S.box[1], S.cell_w[1], S.nc[1], S.periodic[1]),
+                           cell_coord(qi2, S.box[2], S.cell_w[2], S.nc[2], S.periodic[2])};
+        for (int c = 0; c < 27; ++c) {
+            const int64_t cell = stencil_lane_cell(S, cc, c);
+            if (cell < 0) continue;
+            const int cn = d.cell_count[cell];
+            const int c0 = d.cell_start[cell];
             for (int e = 0; e < cn; ++e) {
-                const int j = cs[e];
-                if (j == i || d.type[j] != ti) continue;
-                double dx = d.qx[j] - qi0, dy = d.qy[j] - qi1, dz = d.qz[j] - qi2;
+                const int jt = d.cell_sites[c0 + e];
+                const int j = jt >> 2;
+                if (j == i || (jt & 3) != ti) continue;
+                const double4 rj = d.cell_rec[c0 + e];
+                double dx = rj.x - qi0, dy = rj.y - qi1, dz = rj.z - qi2;
                 min_image(S, dx, dy, dz);
                 if (dx * dx + dy * dy + dz * dz >= rb2) continue;
                 if (n >= B) {
@@ -440,44 +472,48 @@ __global__ __launch_bounds__(kChunk) void k_half(Dev d) {
     if (i < ch.end) d.half_off[i] = d.chunk_off[blockIdx.x] + lds[t] - u;
 }
 
+// One wavefront per site, lanes over its row: the pair id of an entry (i, j)
+// is owned by the lower site; for j < i it is found by binary search of i in
+// j's sorted row (i lies in j's upper part).
 __global__ __launch_bounds__(kChunk) void k_pid(Dev d) {
     const Chunk ch = d.chunks[blockIdx.x];
     const int s = ch.sys;
     if (!d.ctl[s].rebuild) return;
-    const int i = ch.start + threadIdx.x;
-    if (i >= ch.end) return;
     const SysDesc& S = d.sys[s];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int K = d.K;
-    const int cnt = d.nbr_cnt[i], lo = d.nbr_lo[i], hoff = d.half_off[i];
-    const int* row = d.nbr + (int64_t)i * K;
-    int* prow = d.pid + (int64_t)i * K;
     bool bad = false;
-    for (int k = 0; k < cnt; ++k) {
-        const int j = row[k];
-        int local;
-        if (j > i) {
-            local = hoff + (k - lo);
-            if (local < S.pair_cap) {
-                const int64_t p = S.pair_base + local;
-                d.pair_i[p] = i;
-                d.pair_j[p] = j;
+    for (int i = ch.start + wave; i < ch.end; i += kChunk / kWave) {
+        const int cnt = d.nbr_cnt[i], lo = d.nbr_lo[i], hoff = d.half_off[i];
+        const int* row = d.nbr + (int64_t)i * K;
+        int* prow = d.pid + (int64_t)i * K;
+        for (int k = lane; k < cnt; k += kWave) {
+            const int j = row[k];
+            int local;
+            if (j > i) {
+                local = hoff + (k - lo);
+                if (local < S.pair_cap) {
+                    const int64_t p = S.pair_base + local;
+                    d.pair_i[p] = i;
+                    d.pair_j[p] = j;
+                }
+            } else {
+                const int* rj = d.nbr + (int64_t)j * K;
+                const int cj = d.nbr_cnt[j];
+                int l = 0, h = cj;
+                while (l < h) {
+                    const int mid = (l + h) >> 1;
+                    if (rj[mid] < i) l = mid + 1; else h = mid;
+                }
+                if (l >= cj || rj[l] != i) {
+                    bad = true;
+                    prow[k] = -1;
+                    continue;
+                }
+                local = d.half_off[j] + (l - d.nbr_lo[j]);
             }
-        } else {
-            // position of i in j's sorted row; i > j lies in j's upper part
-            const int* rj = d.nbr + (int64_t)j * K;
-            int l = 0, h = d.nbr_cnt[j];
-            while (l < h) {
-                const int mid = (l + h) >> 1;
-                if (rj[mid] < i) l = mid + 1; else h = mid;
-            }
-            if (l >= d.nbr_cnt[j] || rj[l] != i) {
-                bad = true;
-                prow[k] = -1;
-                continue;
-            }
-            local = d.half_off[j] + (l - d.nbr_lo[j]);
+            prow[k] = (local < S.pair_cap) ? (int)(S.pair_base + local) : -1;
         }
-        prow[k] = (local < S.pair_cap) ? (int)(S.pair_base + local) : -1;
     }
     if (bad) atomicOr(&d.ctl[s].status, MXE_STAT_KMAX);
 }
@@ -503,8 +539,6 @@ void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s) {
     k_bin<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_fill<<<d.n_chunks, kChunk, 0, s>>>(d);
-    const int gc = (int)std::min<int64_t>(2048, (d.n_cells + 255) / 256);
-    k_sort_cells<<<gc, 256, 0, s>>>(d);
     const int K2 = row_pow2(d.K);
     k_nbr<<<d.n_chunks, kChunk, (size_t)(kChunk / kWave) * K2 * sizeof(int), s>>>(d, m, K2);
     if (bonds) k_bonds<<<d.n_chunks, kChunk, 0, s>>>(d, m);

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kChunk) void k_mstep_ctl(Dev d, Model m, double dt_
     out[MXE_S_TIME] += dt;
 }
 
-__global__ __launch_bounds__(kChunk) void k_euler(Dev d) {
+__global__ __launch_bounds__(kChunk) void k_euler(Dev d, Model m) {
     __shared__ double lds[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
     const int i = ch.start + threadIdx.x;
@@ -255,6 +255,7 @@ __global__ __launch_bounds__(kChunk) void k_euler(Dev d) {
         if (occ_mobile(d.type[i])) {
             xi += d.ctl[ch.sys].dt_master * d.dxdt[i];
             d.x[i] = xi;
+            d.emit[i] = mixval(m.b4, d.type[i], xi);
             if (!(xi >= -1e-12 && xi <= 1.0 + 1e-12)) atomicOr(&d.ctl[ch.sys].status, MXE_STAT_X_RANGE);
         }
     }
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(kChunk) void k_estep_ctl(Dev d) {
 void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s) {
     k_flux<<<d.n_chunks, kChunk, 0, s>>>(d, m);
     k_mstep_ctl<<<d.n_sys, kChunk, 0, s>>>(d, m, dt_in);
-    k_euler<<<d.n_chunks, kChunk, 0, s>>>(d);
+    k_euler<<<d.n_chunks, kChunk, 0, s>>>(d, m);
     k_estep_ctl<<<d.n_sys, kChunk, 0, s>>>(d);
 }
 
