@@ -190,8 +190,29 @@ void mxe_plan_destroy(mxe_plan* plan);
  * every call of a run. */
 mxe_status mxe_workspace_bytes(const mxe_plan* plan, size_t* bytes);
 
-/* Total number of sites of the plan (length of every per-site array). */
+/* Total number of sites of the plan (length of every per-site array): the sum
+ * of the slot capacities. */
 int64_t mxe_plan_sites(const mxe_plan* plan);
+
+/* Batching with slots. Each system given to mxe_plan_create is a slot whose
+ * n_sites is the slot's capacity; the slot's sites occupy the range
+ * [mxe_plan_slot_offset(slot), mxe_plan_slot_offset(slot + 1)) of every
+ * per-site array. mxe_plan_set_system rebinds a slot to another system of at
+ * most that many sites (its first n_sites entries of the range; n_sites = 0
+ * leaves the slot empty), with its own box, periodicity and temperature. The
+ * change applies from the next call; launch shapes do not change, so recorded
+ * graphs stay valid. Returns MXE_ERANGE if the system does not fit the slot
+ * (sites, or cells of its box), MXE_EINVAL for a bad box or temperature. A
+ * system's results do not depend on its slot, its capacity or the other slots. */
+mxe_status mxe_plan_set_system(mxe_plan* plan, int slot, const mxe_system* sys);
+/* First site of a slot; slot == n_systems gives the total. -1 if out of range. */
+int64_t mxe_plan_slot_offset(const mxe_plan* plan, int slot);
+/* Resume mode. Off (default): every call rebuilds all neighbour lists and
+ * bonds, since the caller may have changed any state between calls. On: calls
+ * rebuild only slots rebound since the previous call (and everything on a
+ * workspace the plan has not used before); the caller must not modify the
+ * positions or widths of other slots between calls. */
+mxe_status mxe_plan_set_resume(mxe_plan* plan, int on);
 
 /* One evaluation at the current state: pass 1 (rho_bar, rho0, the Taylor
  * embedding G, A, B of Eq. F_taylor_mxe) and pass 2 (forces, mu, e_site);

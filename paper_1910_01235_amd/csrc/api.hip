@@ -35,7 +35,13 @@ struct mxe_plan {
     mxe_eam e;
     Model model;
     int n_sys = 0;
-    std::vector<mxe_system> systems;
+    std::vector<mxe_system> systems;        // current system of each slot
+    std::vector<int64_t> cap_sites, cap_cells;  // slot capacities
+    double r_cap = 0.0, r_cell = 0.0;
+    std::vector<char> dirty;     // slot rebound since the last call
+    bool resume = false;         // calls rebuild only dirty slots
+    bool tables_dirty = true;    // chunk tables changed since the last upload
+    void* tables_ws = nullptr;   // workspace that holds the uploaded tables
     std::vector<SysDesc> sys;
     std::vector<Chunk> chunks, pchunks;
     int64_t n_sites = 0, n_cells = 0, pair_cap_total = 0;
@@ -55,6 +61,86 @@ struct mxe_plan {
     std::vector<std::pair<int, size_t>> prof_marks;  // (family, index of start event)
     hipError_t prof_err = hipSuccess;
 };
+
+namespace {
+
+// Cell grid of a system (validates box and temperature); cells must be at
+// least as wide as the largest list radius the plan allows.
+mxe_status slot_cells(const mxe_plan* P, const mxe_system& ms, int s, int64_t* ncell) {
+    if (!(ms.T > 0)) return fail(MXE_EINVAL, "system " + std::to_string(s) + ": T must be positive");
+    int64_t n = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(ms.box[a] > 0))
+            return fail(MXE_EINVAL, "system " + std::to_string(s) + ": box lengths must be positive");
+        if (ms.periodic[a] && !(ms.box[a] > 2.0 * P->r_cap))
+            return fail(MXE_EINVAL, "system " + std::to_string(s) +
+                                        ": periodic box length must exceed twice the list radius " +
+                                        std::to_string(P->r_cap));
+        n *= std::max(1, std::min((int)std::floor(ms.box[a] / P->r_cell), 1024));
+    }
+    *ncell = n;
+    return MXE_OK;
+}
+
+// Points slot s at system ms (n_sites <= capacity; 0 leaves the slot empty).
+// Offsets and capacities stay fixed, so recorded graphs remain valid.
+void bind_slot(mxe_plan* P, int s, const mxe_system& ms) {
+    SysDesc& d = P->sys[s];
+    d.n_sites = ms.n_sites;
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        d.box[a] = ms.box[a];
+        d.periodic[a] = ms.periodic[a] ? 1 : 0;
+        const int nc = std::max(1, std::min((int)std::floor(ms.box[a] / P->r_cell), 1024));
+        d.nc[a] = nc;
+        d.cell_w[a] = ms.box[a] / nc;
+        ncell *= nc;
+    }
+    d.n_cells = ms.n_sites > 0 ? ncell : 0;
+    d.kT = kBoltzmannEv * ms.T;
+    d.beta = 1.0 / d.kT;
+    d.D = P->p.nu0 * std::exp(-d.beta * P->p.Qm);
+    for (int c = 0; c < d.n_chunks; ++c) {
+        const int64_t a = (int64_t)c * kChunk;
+        Chunk& ch = P->chunks[d.chunk_first + c];
+        ch.start = (int)(d.site_off + std::min<int64_t>(a, ms.n_sites));
+        ch.end = (int)(d.site_off + std::min<int64_t>(a + kChunk, ms.n_sites));
+    }
+    P->systems[s] = ms;
+    P->dirty[s] = 1;
+    P->tables_dirty = true;
+}
+
+}  // namespace
+
+extern "C" mxe_status mxe_plan_set_system(mxe_plan* P, int slot, const mxe_system* sys) {
+    if (!P || !sys) return fail(MXE_EINVAL, "null argument");
+    if (slot < 0 || slot >= P->n_sys) return fail(MXE_EINVAL, "slot out of range");
+    if (sys->n_sites < 0 || sys->n_sites > P->cap_sites[slot])
+        return fail(MXE_ERANGE, "slot " + std::to_string(slot) + " holds at most " +
+                                    std::to_string(P->cap_sites[slot]) + " sites");
+    if (sys->n_sites > 0) {
+        int64_t ncell = 0;
+        mxe_status r = slot_cells(P, *sys, slot, &ncell);
+        if (r != MXE_OK) return r;
+        if (ncell > P->cap_cells[slot])
+            return fail(MXE_ERANGE, "slot " + std::to_string(slot) + ": box needs " + std::to_string(ncell) +
+                                        " cells, capacity " + std::to_string(P->cap_cells[slot]));
+    }
+    bind_slot(P, slot, *sys);
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_plan_set_resume(mxe_plan* P, int on) {
+    if (!P) return fail(MXE_EINVAL, "null plan");
+    P->resume = on != 0;
+    return MXE_OK;
+}
+
+extern "C" int64_t mxe_plan_slot_offset(const mxe_plan* P, int slot) {
+    if (!P || slot < 0 || slot > P->n_sys) return -1;
+    return slot == P->n_sys ? P->n_sites : P->sys[slot].site_off;
+}
 
 extern "C" void mxe_default_params(mxe_params* p) {
     std::memset(p, 0, sizeof(*p));
@@ -138,74 +224,55 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     m.dt_safety = p.dt_safety;
 
     // largest list radius the cells must cover
-    const double r_cap = eam->r_c + 3.0 * std::sqrt(2.0) * p.sigma_cap + p.skin;
-    const double r_cell = std::max(r_cap, p.r_bond);
+    P->r_cap = eam->r_c + 3.0 * std::sqrt(2.0) * p.sigma_cap + p.skin;
+    P->r_cell = std::max(P->r_cap, p.r_bond);
     int64_t site_off = 0, cell_off = 0, pair_base = 0;
+    P->sys.resize(n_systems);
+    P->dirty.assign(n_systems, 1);
+    P->cap_sites.resize(n_systems);
+    P->cap_cells.resize(n_systems);
     for (int s = 0; s < n_systems; ++s) {
         const mxe_system& ms = systems[s];
         if (ms.n_sites < 1) {
             delete P;
             return fail(MXE_EINVAL, "system " + std::to_string(s) + ": n_sites < 1");
         }
-        if (!(ms.T > 0)) {
+        int64_t ncell = 0;
+        mxe_status r = slot_cells(P, ms, s, &ncell);
+        if (r != MXE_OK) {
             delete P;
-            return fail(MXE_EINVAL, "system " + std::to_string(s) + ": T must be positive");
+            return r;
         }
-        SysDesc d;
+        // capacities: the given system, and room for the cells of any dense
+        // system of up to n_sites sites (a slot can be rebound later)
+        P->cap_sites[s] = ms.n_sites;
+        P->cap_cells[s] = std::max<int64_t>(ncell, ms.n_sites / 8 + 64);
+        SysDesc& d = P->sys[s];
         std::memset(&d, 0, sizeof(d));
         d.site_off = site_off;
-        d.n_sites = ms.n_sites;
-        int64_t ncell = 1;
-        for (int a = 0; a < 3; ++a) {
-            if (!(ms.box[a] > 0)) {
-                delete P;
-                return fail(MXE_EINVAL, "system " + std::to_string(s) + ": box lengths must be positive");
-            }
-            d.box[a] = ms.box[a];
-            d.periodic[a] = ms.periodic[a] ? 1 : 0;
-            if (d.periodic[a] && !(ms.box[a] > 2.0 * r_cap)) {
-                delete P;
-                return fail(MXE_EINVAL, "system " + std::to_string(s) +
-                                            ": periodic box length must exceed twice the list radius " +
-                                            std::to_string(r_cap));
-            }
-            int nc = (int)std::floor(ms.box[a] / r_cell);
-            nc = std::max(1, std::min(nc, 1024));
-            d.nc[a] = nc;
-            d.cell_w[a] = ms.box[a] / nc;
-            ncell *= nc;
-        }
         d.cell_off = cell_off;
-        d.n_cells = ncell;
         d.pair_base = pair_base;
         d.pair_cap = (ms.n_sites * (int64_t)p.k_max + 1) / 2;
-        d.kT = kBoltzmannEv * ms.T;
-        d.beta = 1.0 / d.kT;
-        d.D = p.nu0 * std::exp(-d.beta * p.Qm);
         d.chunk_first = (int)P->chunks.size();
-        for (int64_t a = 0; a < ms.n_sites; a += kChunk) {
-            Chunk c{s, (int)(site_off + a), (int)(site_off + std::min<int64_t>(ms.n_sites, a + kChunk)), 0};
-            P->chunks.push_back(c);
-        }
+        for (int64_t a = 0; a < ms.n_sites; a += kChunk) P->chunks.push_back(Chunk{s, 0, 0, 0});
         d.n_chunks = (int)P->chunks.size() - d.chunk_first;
         for (int64_t a = 0; a < d.pair_cap; a += kPairChunk) {
             Chunk c{s, (int)(pair_base + a), (int)(pair_base + std::min<int64_t>(d.pair_cap, a + kPairChunk)), 0};
             P->pchunks.push_back(c);
         }
-        P->sys.push_back(d);
         site_off += ms.n_sites;
-        cell_off += ncell;
+        cell_off += P->cap_cells[s];
         pair_base += d.pair_cap;
     }
     P->n_sites = site_off;
     P->n_cells = cell_off;
     P->pair_cap_total = pair_base;
     if (site_off * (int64_t)p.k_max >= (int64_t)INT32_MAX || pair_base >= (int64_t)INT32_MAX ||
-        site_off * 4 >= (int64_t)INT32_MAX ||
-        cell_off >= (int64_t)INT32_MAX) {
+        site_off * 4 >= (int64_t)INT32_MAX || cell_off >= (int64_t)INT32_MAX) {
         delete P;
         return fail(MXE_ERANGE, "plan too large for 32-bit indices");
     }
+    for (int s = 0; s < n_systems; ++s) bind_slot(P, s, systems[s]);
 
     // workspace layout
     const size_t A = 256;
@@ -357,11 +424,24 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
 }
 
 // Tables are re-uploaded at every call so a workspace needs no separate setup.
+// Uploads the system descriptors (with this call's rebuild requests) and, when
+// they changed or the workspace differs, the chunk tables; then initialises
+// the call and builds the lists of every system that must be rebuilt.
 mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, bool bonds) {
+    // a workspace the plan has not used before holds no lists: build everything
+    const bool new_ws = P->tables_ws != (void*)d.sys;
+    for (int k = 0; k < P->n_sys; ++k)
+        P->sys[k].force_build = (!P->resume || new_ws || P->dirty[k]) ? 1 : 0;
     HIP_OK(hipMemcpyAsync(d.sys, P->sys.data(), sizeof(SysDesc) * P->sys.size(), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(d.chunks, P->chunks.data(), sizeof(Chunk) * P->chunks.size(), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(d.pchunks, P->pchunks.data(), sizeof(Chunk) * P->pchunks.size(),
-                          hipMemcpyHostToDevice, s));
+    if (P->tables_dirty || new_ws) {
+        HIP_OK(hipMemcpyAsync(d.chunks, P->chunks.data(), sizeof(Chunk) * P->chunks.size(),
+                              hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(d.pchunks, P->pchunks.data(), sizeof(Chunk) * P->pchunks.size(),
+                              hipMemcpyHostToDevice, s));
+        P->tables_dirty = false;
+        P->tables_ws = (void*)d.sys;
+    }
+    std::fill(P->dirty.begin(), P->dirty.end(), 0);
     launch_ws_init(d, s);
     launch_sys_init(d, P->model, s);
     launch_build(d, P->model, bonds, s);

@@ -38,6 +38,8 @@ struct SysDesc {
     int periodic[3];
     double kT, beta, D;
     int chunk_first, n_chunks;
+    int force_build;  // rebuild lists and bonds at the start of the call
+    int pad;
 };
 
 struct SysCtl {

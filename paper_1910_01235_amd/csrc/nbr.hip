@@ -95,14 +95,18 @@ __global__ void k_sys_init(Dev d) {
     if (s >= d.n_sys) return;
     SysCtl& c = d.ctl[s];
     c.sigmax_bits = 0ull;
-    c.rebuild = 1;
+    // A forced system rebuilds everything; otherwise its lists, pair count and
+    // any pending rebuild request carry over from the previous call.
+    if (d.sys[s].force_build) {
+        c.rebuild = 2;
+        c.n_pairs = 0;
+    }
     c.status = 0;
     c.n_rebuilds = 0;
     c.total_evals = 0;
     c.pair_evals = 0.0;
     c.done = 0;
     c.k = 0;
-    c.n_pairs = 0;
 }
 
 // widths and occupancies are checked, and the largest width recorded
@@ -385,6 +389,7 @@ __global__ __launch_bounds__(kChunk) void k_bonds(Dev d, Model m) {
     const int i = ch.start + threadIdx.x;
     if (i >= ch.end) return;
     const int s = ch.sys;
+    if (!d.sys[s].force_build) return;  // bonds of the other systems are kept
     const SysDesc& S = d.sys[s];
     const int B = d.bond_max;
     const int ti = d.type[i];

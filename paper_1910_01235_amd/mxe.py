@@ -27,8 +27,9 @@ FATAL_STATUS = STAT_NONFINITE | STAT_X_RANGE | STAT_RHO | STAT_KMAX | STAT_PAIRS
     STAT_SIGMA_CAP
 
 EXPORTED = ["mxe_default_params", "mxe_plan_create", "mxe_plan_destroy", "mxe_workspace_bytes",
-            "mxe_plan_sites", "mxe_evaluate", "mxe_relax", "mxe_step", "mxe_run",
-            "mxe_profile", "mxe_profile_read", "mxe_status_string", "mxe_last_error"]
+            "mxe_plan_sites", "mxe_plan_set_system", "mxe_plan_slot_offset", "mxe_plan_set_resume",
+            "mxe_evaluate", "mxe_relax", "mxe_step", "mxe_run", "mxe_profile", "mxe_profile_read",
+            "mxe_status_string", "mxe_last_error"]
 
 
 class Eam(C.Structure):
@@ -82,6 +83,12 @@ def lib():
         L.mxe_workspace_bytes.restype = C.c_int
         L.mxe_plan_sites.argtypes = [C.c_void_p]
         L.mxe_plan_sites.restype = C.c_int64
+        L.mxe_plan_set_system.argtypes = [C.c_void_p, C.c_int, C.POINTER(System)]
+        L.mxe_plan_set_system.restype = C.c_int
+        L.mxe_plan_slot_offset.argtypes = [C.c_void_p, C.c_int]
+        L.mxe_plan_slot_offset.restype = C.c_int64
+        L.mxe_plan_set_resume.argtypes = [C.c_void_p, C.c_int]
+        L.mxe_plan_set_resume.restype = C.c_int
         for name in ("mxe_evaluate", "mxe_relax"):
             getattr(L, name).argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Out), C.c_void_p,
                                          C.c_size_t, C.c_void_p]
@@ -223,7 +230,25 @@ class Plan:
         _check(L.mxe_workspace_bytes(h, C.byref(nb)))
         self.ws_bytes = int(nb.value)
         self.n_sites = int(L.mxe_plan_sites(h))
-        self.offsets = np.cumsum([0] + [int(s.n) for s in systems])
+        self.offsets = np.array([int(L.mxe_plan_slot_offset(h, k)) for k in range(len(systems) + 1)])
+
+    @staticmethod
+    def _system(s) -> System:
+        m = System()
+        m.n_sites = int(s.n) if s is not None else 0
+        for a in range(3):
+            m.box[a] = float(s.box[a]) if s is not None else 100.0
+            m.periodic[a] = int(bool(s.periodic[a])) if s is not None else 0
+        m.T = float(s.T) if s is not None else 300.0
+        return m
+
+    def set_system(self, slot: int, s):
+        """Rebind a slot to system s (None empties it); applies from the next call."""
+        m = self._system(s)
+        _check(lib().mxe_plan_set_system(self._h, int(slot), C.byref(m)))
+
+    def set_resume(self, on: bool):
+        _check(lib().mxe_plan_set_resume(self._h, int(bool(on))))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -1,0 +1,256 @@
+"""Continuous batching of many independent systems on one GPU.
+
+Requests (a system, a number of diffusion steps, an arrival time) are served
+from a pool of plan slots sized to an HBM budget. At every step boundary the
+server admits the requests that have arrived into free slots (the smallest
+free slot that holds the system), then advances every resident system by one
+diffusion step of the staggered scheme with one replay of the recorded graph,
+and retires the systems that have finished. Requests that arrive while others
+run join as slots free up; their work shares every launch with the resident
+systems. A system's results do not depend on its slot or its batch-mates.
+
+The one-at-a-time path serves the same stream with a single-slot plan per
+request, in arrival order, for comparison on the same GPU.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import lattice as L
+from . import mxe
+
+STATE_BYTES_PER_SITE = 14 * 8 + 1  # q(3), sigma, x, 9 outputs (FP64), type (int8)
+
+
+@dataclass
+class Request:
+    rid: int
+    system: L.System
+    n_steps: int
+    arrival: float = 0.0  # seconds after the start of serving
+
+
+@dataclass
+class Result:
+    rid: int
+    n_sites: int
+    slot: int
+    arrival: float
+    admitted: float
+    completed: float
+    x: np.ndarray
+    q: np.ndarray
+    sigma: np.ndarray
+    time_simulated: float
+    status: int
+
+    @property
+    def latency(self) -> float:
+        return self.completed - self.arrival
+
+
+def bytes_per_site(eam: dict, params: dict, precision: str = "fp64", probe_sites: int = 4096) -> float:
+    """Device bytes per site of a slot: workspace plus state and outputs (host-side probe)."""
+    n_cells = max(6, int(round((probe_sites / 4) ** (1 / 3))))
+    s = L.vacancy_bulk(n_cells, 0, 300.0, 0)
+    plan = mxe.Plan([s], eam, params, precision=precision)
+    return plan.ws_bytes / s.n + STATE_BYTES_PER_SITE
+
+
+def pool_capacities(budget_bytes: float, per_site: float, classes=(1024, 2048, 4096, 8192, 16384,
+                                                                     32768, 65536)) -> list:
+    """Equal numbers of slots per capacity class, as many as the budget holds.
+
+    Request sizes drawn log-uniformly fall equally often in each octave, so each
+    class gets the same number of slots. Returns the slot capacities (sites)."""
+    per_round = sum(classes) * per_site
+    m = int(budget_bytes // per_round)
+    if m < 1:
+        raise ValueError(f"budget {budget_bytes:.3g} B holds no slot of every class "
+                         f"({per_round:.3g} B needed)")
+    return [c for c in classes for _ in range(m)]
+
+
+def pick_slot(capacities: list, free, n: int):
+    """Smallest free slot that holds n sites (lowest index among equals), or None."""
+    best = None
+    for k in sorted(free):
+        c = capacities[k]
+        if c >= n and (best is None or c < capacities[best]):
+            best = k
+    return best
+
+
+def _template(capacity: int, r_min_box: float) -> L.System:
+    """Placeholder system that defines a slot's capacity (slots start empty)."""
+    side = max(r_min_box, (capacity * 11.8) ** (1.0 / 3.0))
+    n = capacity
+    return L.System(np.zeros((n, 3)), np.full(n, 0.1), np.ones(n), np.zeros(n, np.int8),
+                    (side, side, side), (True, True, True), 300.0, f"slot{capacity}")
+
+
+class Server:
+    """A pool of slots on one GPU, with continuous batching over diffusion steps."""
+
+    def __init__(self, eam: dict, params: dict, capacities: list, precision: str = "fp64",
+                 device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.capacities = list(capacities)
+        r_cap = eam["r_c"] + 3 * math.sqrt(2) * params.get("sigma_cap", 0.3) + params.get("skin", 0.15)
+        templates = [_template(c, 2 * r_cap + 1.0) for c in self.capacities]
+        self.plan = mxe.Plan(templates, eam, params, precision=precision)
+        for k in range(len(templates)):
+            self.plan.set_system(k, None)
+        self.plan.set_resume(True)
+        N = self.plan.n_sites
+        z = lambda: torch.zeros(N, dtype=torch.float64, device=device)
+        self.st = mxe.DeviceState(z(), z(), z(), torch.full((N,), 0.1, dtype=torch.float64, device=device),
+                                  z(), torch.zeros(N, dtype=torch.int8, device=device))
+        self.out = self.plan.out(device)
+        self.ws = self.plan.workspace(device)
+        self.free = set(range(len(templates)))
+        self.device = device
+
+    @property
+    def footprint_bytes(self) -> int:
+        return self.ws.numel() + self.plan.n_sites * STATE_BYTES_PER_SITE
+
+    def fits(self, n: int) -> bool:
+        return n <= max(self.capacities)
+
+    def pick_slot(self, n: int):
+        return pick_slot(self.capacities, self.free, n)
+
+    def admit(self, slot: int, s: L.System):
+        torch = self.torch
+        off = int(self.plan.offsets[slot])
+        n = s.n
+        self.plan.set_system(slot, s)
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=self.device)
+        self.st.qx[off:off + n] = f(s.q[:, 0])
+        self.st.qy[off:off + n] = f(s.q[:, 1])
+        self.st.qz[off:off + n] = f(s.q[:, 2])
+        self.st.sigma[off:off + n] = f(s.sigma)
+        self.st.x[off:off + n] = f(s.x)
+        self.st.type[off:off + n] = torch.as_tensor(s.type.astype(np.int8), device=self.device)
+        self.out.scalars[slot * mxe.NSCALARS + mxe.S_TIME] = 0.0
+        self.free.discard(slot)
+
+    def collect(self, slot: int, n: int):
+        off = int(self.plan.offsets[slot])
+        g = lambda t: t[off:off + n].cpu().numpy()
+        q = np.stack([g(self.st.qx), g(self.st.qy), g(self.st.qz)], axis=1)
+        sc = self.out.scalars[slot * mxe.NSCALARS:(slot + 1) * mxe.NSCALARS].cpu().numpy()
+        return g(self.st.x), q, g(self.st.sigma), float(sc[mxe.S_TIME]), int(sc[mxe.S_STATUS])
+
+    def retire(self, slot: int):
+        self.plan.set_system(slot, None)
+        self.free.add(slot)
+
+    def step(self):
+        self.plan.run(self.st, self.out, self.ws, 1, use_graph=True)
+
+    def serve(self, requests: list, realtime: bool = True):
+        """Serve a request stream; returns (results, rejected ids, stats)."""
+        torch = self.torch
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        n_steps_of = {r.rid: r.n_steps for r in pending}
+        rejected = [r.rid for r in pending if not self.fits(r.system.n)]
+        pending = [r for r in pending if self.fits(r.system.n)]
+        active = {}  # slot -> [request, steps done, admitted time]
+        results = []
+        steps = 0
+        busy = 0.0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        while pending or active:
+            t = now()
+            # admit arrived requests in arrival order while slots are free
+            keep = []
+            for r in pending:
+                if realtime and r.arrival > t:
+                    keep.append(r)
+                    continue
+                slot = self.pick_slot(r.system.n)
+                if slot is None:
+                    keep.append(r)
+                    continue
+                self.admit(slot, r.system)
+                active[slot] = [r, 0, now()]
+            pending = keep
+            if not active:
+                if pending and realtime:
+                    time.sleep(max(0.0, min(p.arrival for p in pending) - now()))
+                continue
+            ts = now()
+            self.step()
+            torch.cuda.synchronize()
+            busy += now() - ts
+            steps += 1
+            done = []
+            for slot, rec in active.items():
+                rec[1] += 1
+                if rec[1] >= rec[0].n_steps:
+                    done.append(slot)
+            tc = now()
+            for slot in done:
+                r, _, ta = active.pop(slot)
+                x, q, sg, tsim, st = self.collect(slot, r.system.n)
+                results.append(Result(r.rid, r.system.n, slot, r.arrival, ta, tc, x, q, sg, tsim, st))
+                self.retire(slot)
+        makespan = now()
+        lat = np.array([r.latency for r in results]) if results else np.zeros(1)
+        stats = dict(systems=len(results), rejected=len(rejected), makespan_s=makespan,
+                     systems_per_s=len(results) / makespan if makespan > 0 else 0.0,
+                     site_steps_per_s=(sum(r.n_sites * n_steps_of[r.rid] for r in results) / makespan
+                                       if makespan > 0 else 0.0),
+                     p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                     gpu_steps=steps, gpu_busy_s=busy, footprint_bytes=self.footprint_bytes,
+                     slots=len(self.capacities))
+        return results, rejected, stats
+
+
+def serve_one_at_a_time(eam: dict, params: dict, requests: list, precision: str = "fp64",
+                        realtime: bool = True, device: str = "cuda"):
+    """The plain path: each request alone on its own plan, in arrival order."""
+    import torch
+    results = []
+    pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0
+    for r in pending:
+        if realtime and r.arrival > now():
+            time.sleep(r.arrival - now())
+        ta = now()
+        plan = mxe.Plan([r.system], eam, params, precision=precision)
+        st, out, ws = plan.state([r.system], device), plan.out(device), plan.workspace(device)
+        plan.run(st, out, ws, r.n_steps, use_graph=True)
+        torch.cuda.synchronize()
+        tc = now()
+        sc = plan.scalars(out)[0]
+        q = torch.stack([st.qx, st.qy, st.qz], 1).cpu().numpy()
+        results.append(Result(r.rid, r.system.n, 0, r.arrival, ta, tc, st.x.cpu().numpy(), q,
+                              st.sigma.cpu().numpy(), float(sc[mxe.S_TIME]), int(sc[mxe.S_STATUS])))
+        del plan, st, out, ws
+    makespan = now()
+    lat = np.array([r.latency for r in results]) if results else np.zeros(1)
+    stats = dict(systems=len(results), makespan_s=makespan,
+                 systems_per_s=len(results) / makespan if makespan > 0 else 0.0,
+                 p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)))
+    return results, stats
+
+
+def poisson_requests(systems: list, n_steps: int, rate: float, seed: int = 0) -> list:
+    """Requests with exponential inter-arrival times at `rate` per second."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k, s in enumerate(systems):
+        out.append(Request(k, s, n_steps, t))
+        t += float(rng.exponential(1.0 / rate)) if rate > 0 else 0.0
+    return out

@@ -1,0 +1,128 @@
+"""Batched systems of uneven size in one launch sequence, slots, continuous batching.
+
+Each system's results must equal its single-system run bitwise: the kernels are
+deterministic and a system's reductions do not depend on its slot, capacity or
+batch-mates."""
+import numpy as np
+import pytest
+
+from paper_1910_01235_amd import lattice as L
+from paper_1910_01235_amd import serve
+from tests.gpu_common import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mx():
+    from paper_1910_01235_amd import mxe
+    mxe.lib()
+    assert torch.cuda.is_available(), "no HIP device"
+    return mxe
+
+
+def _mixed_systems():
+    return [L.vacancy_bulk(5, 1, 700.0, 1, name="vac5"),
+            L.alloy_bulk(6, 0.06, 1100.0, 2, name="alloy6"),
+            L.vacancy_bulk(7, 1, 950.0, 3, name="vac7"),
+            L.alloy_bulk(5, 0.02, 620.0, 4, name="alloy5")]
+
+
+def _run_alone(mx, s, params, n_steps, precision="fp64"):
+    plan = mx.Plan([s], L.DEFAULT_EAM, params, precision=precision)
+    st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+    plan.run(st, out, ws, n_steps, use_graph=True)
+    torch.cuda.synchronize()
+    return (st.x.cpu().numpy(), torch.stack([st.qx, st.qy, st.qz], 1).cpu().numpy(),
+            st.sigma.cpu().numpy(), plan.scalars(out)[0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_plan_equals_single_runs_bitwise(mx, precision):
+    systems = _mixed_systems()
+    params = dict(L.DEFAULT_PARAMS, max_relax=20)
+    say(f"[gpu] batched {len(systems)} systems {precision}")
+    plan = mx.Plan(systems, L.DEFAULT_EAM, params, precision=precision)
+    st, out, ws = plan.state(systems), plan.out(), plan.workspace()
+    plan.run(st, out, ws, 3, use_graph=True)
+    torch.cuda.synchronize()
+    sc = plan.scalars(out)
+    for k, s in enumerate(systems):
+        lo, hi = plan.offsets[k], plan.offsets[k + 1]
+        x, q, sg, sc1 = _run_alone(mx, s, params, 3, precision)
+        assert np.array_equal(st.x[lo:hi].cpu().numpy(), x), s.name
+        assert np.array_equal(st.sigma[lo:hi].cpu().numpy(), sg), s.name
+        assert np.array_equal(st.qx[lo:hi].cpu().numpy(), q[:, 0]), s.name
+        assert sc[k, mx.S_TIME] == sc1[mx.S_TIME]
+        assert int(sc[k, mx.S_STATUS]) & mx.FATAL_STATUS == 0
+
+
+def test_slots_rebind_with_resume(mx):
+    """Slots larger than their systems, rebound between calls, in resume mode."""
+    a, b, c = _mixed_systems()[:3]
+    params = dict(L.DEFAULT_PARAMS, max_relax=15)
+    tmpl = [L.vacancy_bulk(8, 0, 300.0, 0), L.vacancy_bulk(8, 0, 300.0, 0)]  # 2048-site slots
+    plan = mx.Plan(tmpl, L.DEFAULT_EAM, params)
+    plan.set_resume(True)
+    N = plan.n_sites
+    st = mx.DeviceState(*[torch.zeros(N, dtype=torch.float64, device="cuda") for _ in range(5)],
+                        torch.zeros(N, dtype=torch.int8, device="cuda"))
+    st.sigma.fill_(0.1)
+    out, ws = plan.out(), plan.workspace()
+
+    def load(slot, s):
+        plan.set_system(slot, s)
+        off = int(plan.offsets[slot])
+        for name, arr in (("qx", s.q[:, 0]), ("qy", s.q[:, 1]), ("qz", s.q[:, 2]), ("sigma", s.sigma),
+                          ("x", s.x)):
+            getattr(st, name)[off:off + s.n] = torch.as_tensor(arr, device="cuda")
+        st.type[off:off + s.n] = torch.as_tensor(s.type, device="cuda")
+        out.scalars[slot * mx.NSCALARS + mx.S_TIME] = 0.0
+
+    load(0, a)
+    load(1, b)
+    for _ in range(2):
+        plan.run(st, out, ws, 1, use_graph=True)
+    plan.set_system(0, None)         # slot 0 retires a; slot 1 keeps b
+    load(0, c)
+    plan.run(st, out, ws, 2, use_graph=True)
+    torch.cuda.synchronize()
+    xb, _, _, _ = _run_alone(mx, b, params, 4)
+    xc, _, sgc, _ = _run_alone(mx, c, params, 2)
+    o0, o1 = int(plan.offsets[0]), int(plan.offsets[1])
+    assert np.array_equal(st.x[o1:o1 + b.n].cpu().numpy(), xb)
+    assert np.array_equal(st.x[o0:o0 + c.n].cpu().numpy(), xc)
+    assert np.array_equal(st.sigma[o0:o0 + c.n].cpu().numpy(), sgc)
+    with pytest.raises(mx.MxeError, match="holds at most"):
+        plan.set_system(0, L.vacancy_bulk(9, 0, 300.0, 0))
+
+
+def test_served_results_equal_alone(mx):
+    params = dict(L.DEFAULT_PARAMS, max_relax=15)
+    rng = np.random.default_rng(7)
+    systems = []
+    for k in range(7):
+        cells = int(rng.integers(5, 9))
+        T = float(rng.uniform(600, 1200))
+        systems.append(L.vacancy_bulk(cells, 1, T, k) if k % 2 else L.alloy_bulk(cells, 0.05, T, k))
+    systems.append(L.vacancy_bulk(12, 1, 800.0, 99))  # 6912 sites: too large for the pool
+    reqs = serve.poisson_requests(systems, n_steps=3, rate=0.0)
+    per_site = serve.bytes_per_site(L.DEFAULT_EAM, params)
+    caps = [1024, 1024, 2048, 2048]
+    budget = sum(caps) * per_site * 1.05
+    say("[gpu] serving 8 requests on 4 slots")
+    srv = serve.Server(L.DEFAULT_EAM, params, caps)
+    assert srv.footprint_bytes <= budget
+    results, rejected, stats = srv.serve(reqs, realtime=False)
+    assert rejected == [7]
+    assert len(results) == 7 and stats["gpu_steps"] >= 6
+    alone, _ = serve.serve_one_at_a_time(L.DEFAULT_EAM, params, reqs[:7], realtime=False)
+    by_id = {r.rid: r for r in alone}
+    for r in results:
+        a = by_id[r.rid]
+        assert r.status & mx.FATAL_STATUS == 0
+        assert np.array_equal(r.x, a.x), r.rid
+        assert np.array_equal(r.q, a.q), r.rid
+        assert np.array_equal(r.sigma, a.sigma), r.rid
+        assert r.time_simulated == a.time_simulated
