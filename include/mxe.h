@@ -103,6 +103,12 @@ typedef struct {
     int k_max;           /* neighbour-list row length (max neighbours/site)   */
     int bond_max;        /* max bonds per site                                */
     mxe_precision precision;
+    /* launch shapes (performance only; results do not depend on them beyond
+     * the order of floating-point sums): lanes per site in the gathers
+     * (0 = 8; 8, 16, 32, 64) and threads per block of the pair kernel
+     * (0 = 256; 64, 128, 256) */
+    int gather_lanes;
+    int pair_block;
 } mxe_params;
 
 typedef struct {

@@ -1,0 +1,95 @@
+"""Launch-shape autotuner for the evaluation kernels.
+
+Two launch shapes change speed but not the method: the lanes per site of the
+density and force gathers (8, 16, 32, 64) and the block size of the pair
+quadrature kernel (64, 128, 256). The tuner times every candidate on the
+workload at hand (HIP events around each kernel launch, through the library's
+profiling switch), keeps the fastest, and caches the choice per size bucket,
+precision and lattice kind in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+from . import lattice as L
+from . import mxe
+
+GATHER_LANES = (8, 16, 32, 64)
+PAIR_BLOCKS = (64, 128, 256)
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mxe_autotune.json")
+
+
+def bucket(systems, precision: str) -> str:
+    """Size bucket (power of two of the total sites), precision and lattice kind."""
+    n = sum(int(s.n) for s in systems)
+    kind = "interstitial" if any((s.type == L.INTERSTITIAL).any() for s in systems) else "host"
+    return f"{precision}/{kind}/2^{int(round(math.log2(max(n, 1))))}"
+
+
+class Cache:
+    def __init__(self, path: str = DEFAULT_CACHE):
+        self.path = path
+        self.data = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.data = json.load(f)
+
+    def get(self, key: str):
+        return self.data.get(key)
+
+    def put(self, key: str, value: dict):
+        self.data[key] = value
+        if self.path:
+            os.makedirs(os.path.dirname(self.path) or ".", exist_ok=True)
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.data, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+
+def _time_kernels(systems, eam, params, precision, reps, **shape):
+    import torch
+    plan = mxe.Plan(systems, eam, params, precision=precision, **shape)
+    st, out, ws = plan.state(systems), plan.out(), plan.workspace()
+    plan.evaluate(st, out, ws)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read()
+    for _ in range(reps):
+        plan.evaluate(st, out, ws)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+    del plan, st, out, ws
+    torch.cuda.empty_cache()
+    return ms
+
+
+def tune(systems, eam: dict, params: dict, precision: str = "fp64", reps: int = 5) -> dict:
+    """Time every candidate shape on these systems; return the fastest and the timings."""
+    timings = {"gather_lanes": {}, "pair_block": {}}
+    for g in GATHER_LANES:
+        ms = _time_kernels(systems, eam, params, precision, reps, gather_lanes=g)
+        timings["gather_lanes"][g] = ms["density"] + ms["force"]
+    for b in PAIR_BLOCKS:
+        ms = _time_kernels(systems, eam, params, precision, reps, pair_block=b)
+        timings["pair_block"][b] = ms["pair"]
+    best_g = min(timings["gather_lanes"], key=timings["gather_lanes"].get)
+    best_b = min(timings["pair_block"], key=timings["pair_block"].get)
+    return dict(gather_lanes=int(best_g), pair_block=int(best_b),
+                timings_ms={k: {str(a): round(b, 5) for a, b in v.items()} for k, v in timings.items()})
+
+
+def tuned_params(systems, eam: dict, params: dict, precision: str = "fp64", cache: Cache = None,
+                 retune: bool = False, reps: int = 5):
+    """params with the tuned launch shapes (tuned now, or taken from the cache)."""
+    key = bucket(systems, precision)
+    hit = None if (cache is None or retune) else cache.get(key)
+    if hit is None:
+        hit = tune(systems, eam, params, precision, reps)
+        if cache is not None:
+            cache.put(key, hit)
+    return dict(params, gather_lanes=hit["gather_lanes"], pair_block=hit["pair_block"]), hit

@@ -215,8 +215,8 @@ struct alignas(16) Vec16 {
     T v[n];
 };
 
-template <typename T>
-__global__ __launch_bounds__(256, 3) void k_pair(Dev d, Model m) {
+template <typename T, int kBS>
+__global__ __launch_bounds__(kBS, 3) void k_pair(Dev d, Model m) {
     const Chunk ch = d.pchunks[blockIdx.x];
     const SysCtl& c = d.ctl[ch.sys];
     if (c.done) return;
@@ -251,8 +251,7 @@ __global__ __launch_bounds__(256, 3) void k_pair(Dev d, Model m) {
 
 // Gathers run LPS lanes per site, so one wavefront serves 64 / LPS sites at a
 // time and keeps that many sites' loads in flight.
-constexpr int kLPS = 16;
-constexpr int kGroups = kChunk / kLPS;  // concurrent sites per block
+// kLPS (8, 16, 32 or 64) is chosen per plan (tuned); kGroups sites run per block.
 
 template <int LPS>
 __device__ inline double group_sum(double v) {
@@ -261,8 +260,9 @@ __device__ inline double group_sum(double v) {
     return v;
 }
 
-template <typename T>
+template <typename T, int kLPS>
 __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
+    constexpr int kGroups = kChunk / kLPS;
     const Chunk ch = d.chunks[blockIdx.x];
     if (d.ctl[ch.sys].done) return;
     const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
@@ -339,8 +339,9 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
 // touches one cache line per entry instead of one per lane.
 constexpr int kQ = 4;
 
-template <typename T>
+template <typename T, int kLPS>
 __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
+    constexpr int kGroups = kChunk / kLPS;
     __shared__ double red[kGroups][6];
     const Chunk ch = d.chunks[blockIdx.x];
     const int sys = ch.sys;
@@ -480,19 +481,48 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
     }
 }
 
+template <typename T>
+void launch_pair_t(const Dev& d, const Model& m, int bs, hipStream_t s) {
+    switch (bs) {
+        case 64: k_pair<T, 64><<<d.n_pchunks, 64, 0, s>>>(d, m); break;
+        case 128: k_pair<T, 128><<<d.n_pchunks, 128, 0, s>>>(d, m); break;
+        default: k_pair<T, 256><<<d.n_pchunks, 256, 0, s>>>(d, m); break;
+    }
+}
+
+template <typename T>
+void launch_density_t(const Dev& d, const Model& m, int lps, hipStream_t s) {
+    switch (lps) {
+        case 8: k_density<T, 8><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        case 32: k_density<T, 32><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        case 64: k_density<T, 64><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        default: k_density<T, 16><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+    }
+}
+
+template <typename T>
+void launch_force_t(const Dev& d, const Model& m, int lps, hipStream_t s) {
+    switch (lps) {
+        case 8: k_force<T, 8><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        case 32: k_force<T, 32><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        case 64: k_force<T, 64><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        default: k_force<T, 16><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+    }
+}
+
 void launch_pair(const Dev& d, const Model& m, int precision, hipStream_t s) {
-    if (precision == MXE_FP32_MIXED) k_pair<float><<<d.n_pchunks, 256, 0, s>>>(d, m);
-    else k_pair<double><<<d.n_pchunks, 256, 0, s>>>(d, m);
+    if (precision == MXE_FP32_MIXED) launch_pair_t<float>(d, m, m.pair_block, s);
+    else launch_pair_t<double>(d, m, m.pair_block, s);
 }
 
 void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s) {
-    if (precision == MXE_FP32_MIXED) k_density<float><<<d.n_chunks, kChunk, 0, s>>>(d, m);
-    else k_density<double><<<d.n_chunks, kChunk, 0, s>>>(d, m);
+    if (precision == MXE_FP32_MIXED) launch_density_t<float>(d, m, m.gather_lanes, s);
+    else launch_density_t<double>(d, m, m.gather_lanes, s);
 }
 
 void launch_force(const Dev& d, const Model& m, int precision, hipStream_t s) {
-    if (precision == MXE_FP32_MIXED) k_force<float><<<d.n_chunks, kChunk, 0, s>>>(d, m);
-    else k_force<double><<<d.n_chunks, kChunk, 0, s>>>(d, m);
+    if (precision == MXE_FP32_MIXED) launch_force_t<float>(d, m, m.gather_lanes, s);
+    else launch_force_t<double>(d, m, m.gather_lanes, s);
 }
 
 }  // namespace mxe

@@ -71,6 +71,7 @@ struct Model {
     double ftol, dt0, dtmax, alpha0, finc, fdec, falpha;
     int nmin, max_relax;
     double sigma_min, sigma_cap, skin, r_bond, kin_c, dt_safety;
+    int gather_lanes, pair_block;  // launch shapes (tuned per workload)
 };
 
 // Every device pointer the kernels use.

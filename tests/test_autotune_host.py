@@ -1,0 +1,36 @@
+"""Autotuner host logic: buckets, cache round trip, shape validation by the plan."""
+import pytest
+
+from paper_1910_01235_amd import autotune
+from paper_1910_01235_amd import lattice as L
+from paper_1910_01235_amd import mxe
+
+
+def test_bucket_names():
+    a = [L.vacancy_bulk(4, 0, 800.0, 0)]
+    assert autotune.bucket(a, "fp64") == "fp64/host/2^8"
+    w = L.nanowire(radius=6.0, n_axial=4)
+    assert autotune.bucket([w], "fp32").startswith("fp32/interstitial/")
+
+
+def test_cache_round_trip(tmp_path):
+    p = str(tmp_path / "sub" / "cache.json")
+    c = autotune.Cache(p)
+    assert c.get("k") is None
+    c.put("k", {"gather_lanes": 32, "pair_block": 128})
+    assert autotune.Cache(p).get("k") == {"gather_lanes": 32, "pair_block": 128}
+
+
+def test_plan_validates_launch_shapes():
+    import os
+    if not os.path.exists(mxe.LIB_PATH):
+        pytest.skip("libmxe.so not built")
+    w = L.config0(0)
+    for g in autotune.GATHER_LANES:
+        mxe.Plan(w.systems, w.eam, w.params, gather_lanes=g)
+    for b in autotune.PAIR_BLOCKS:
+        mxe.Plan(w.systems, w.eam, w.params, pair_block=b)
+    with pytest.raises(mxe.MxeError, match="gather_lanes"):
+        mxe.Plan(w.systems, w.eam, w.params, gather_lanes=12)
+    with pytest.raises(mxe.MxeError, match="pair_block"):
+        mxe.Plan(w.systems, w.eam, w.params, pair_block=512)

@@ -126,3 +126,25 @@ def test_served_results_equal_alone(mx):
         assert np.array_equal(r.q, a.q), r.rid
         assert np.array_equal(r.sigma, a.sigma), r.rid
         assert r.time_simulated == a.time_simulated
+
+
+def test_autotuned_shapes_keep_results(mx, tmp_path):
+    """Every launch shape gives the same physics (to rounding); the tuner picks one."""
+    from paper_1910_01235_amd import autotune
+    s = L.jitter(L.vacancy_bulk(6, 4, 900.0, 5), 6, xr=(0.3, 0.9))
+    p = dict(L.DEFAULT_PARAMS)
+    ref = None
+    for g in autotune.GATHER_LANES:
+        for b in (64, 256):
+            plan = mx.Plan([s], L.DEFAULT_EAM, p, gather_lanes=g, pair_block=b)
+            st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+            plan.evaluate(st, out, ws)
+            f = torch.stack([out.fx, out.fy, out.fz, out.fsigma, out.mu], 1).cpu().numpy()
+            if ref is None:
+                ref = f
+            assert np.abs(f - ref).max() <= 1e-13 * np.abs(ref).max(), (g, b)
+    cache = autotune.Cache(str(tmp_path / "tune.json"))
+    params, hit = autotune.tuned_params([s], L.DEFAULT_EAM, p, "fp64", cache=cache, reps=2)
+    assert params["gather_lanes"] in autotune.GATHER_LANES
+    assert params["pair_block"] in autotune.PAIR_BLOCKS
+    assert cache.get(autotune.bucket([s], "fp64")) == hit
