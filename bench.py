@@ -40,6 +40,33 @@ OPS_PER_PAIR = 27 * 90
 BYTES_FORCE_PER_PAIR = 2 * (14 * 8 + 8)
 BYTES_FORCE_PER_SITE = 8 + 8 + 1 + 8 * 3 + 8 * 4 + 8 * 6
 
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
+# this bench (--steps 2 --warmup 1 --no-extras --no-cpu-baseline --calib-copy),
+# KiB per dispatch averaged over the run's dispatches, scaled by what the same
+# counters read for a 1 GiB device copy (FETCH x 2, WRITE x 1). Valid only for
+# the kernel sources they were taken on: a different source hash reports null.
+COUNTER_SCALE = dict(fetch=2.0, write=1.0)
+COUNTERS = dict(
+    sources_sha256_16="07bbd395bfc21132",
+    pair=dict(fetch_kib=80009.2, write_kib=1018955.3),
+    force=dict(fetch_kib=1166584.4, write_kib=13535.3),
+    density=dict(fetch_kib=317785.7, write_kib=27785.8),
+)
+COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
+
+
+def counter_traffic(family: str):
+    """Scaled HBM bytes per launch of a kernel family, or None if the sources changed."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in COUNTER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != COUNTERS["sources_sha256_16"] or family not in COUNTERS:
+        return None
+    c = COUNTERS[family]
+    return (COUNTER_SCALE["fetch"] * c["fetch_kib"] + COUNTER_SCALE["write"] * c["write_kib"]) * 1024.0
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -130,14 +157,16 @@ def main():
     pair_avg_s = fam["pair"]["ms_avg"] / 1e3
     roof_pair = dict(bound="alu", achieved=ops / pair_avg_s / 1e12 if pair_avg_s > 0 else 0.0,
                      peak=PEAK_FP64_TOPS, unit="Tops/s", kernel="k_pair<double>",
-                     traffic=None)
+                     traffic=counter_traffic("pair"), traffic_unit="B/launch")
     roof_pair["frac"] = roof_pair["achieved"] / roof_pair["peak"]
     evals_per_launch = evals / max(fam["force"]["launches"], 1)
     bytes_force = (BYTES_FORCE_PER_PAIR * pair_evals / max(evals, 1) + BYTES_FORCE_PER_SITE * n) \
         * evals_per_launch
     force_avg_s = fam["force"]["ms_avg"] / 1e3
     roof_force = dict(bound="hbm", achieved=bytes_force / force_avg_s / 1e9 if force_avg_s > 0 else 0.0,
-                      peak=PEAK_HBM_GBS, unit="GB/s", kernel="k_force<double>", traffic=None)
+                      peak=PEAK_HBM_GBS, unit="GB/s", kernel="k_force<double>",
+                      traffic=counter_traffic("force"), traffic_unit="B/launch",
+                      algorithmic_bytes=bytes_force)
     roof_force["frac"] = roof_force["achieved"] / roof_force["peak"]
     dominant = max(fam, key=lambda k: fam[k]["ms_total"])
     roofline = roof_pair if dominant != "force" else roof_force
