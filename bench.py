@@ -78,6 +78,7 @@ def cpu_baseline(workload, n_sample: int):
 
     import oracle as O
     s = workload.systems[0]
+    n_sample = min(n_sample, s.n)
     sel = np.arange(n_sample, dtype=np.int32)
     O.lib()
     t0 = time.perf_counter()
@@ -87,6 +88,68 @@ def cpu_baseline(workload, n_sample: int):
                 sample=f"one evaluation (density pass over the sample and its neighbours, force/mu "
                        f"pass over the sample) of the first {n_sample} of {s.n} sites of the "
                        f"initial state; {dt:.2f} s wall")
+
+
+def batched_legs(n_requests: int, n_steps: int, seed: int = 4):
+    """Many independent systems: one batched plan, one at a time, and served.
+
+    Requests: cubic vacancy or alloy systems, sizes log-uniform in [500, 50,000]
+    sites, T in [600, 1200] K. Rates count site-evaluations (sites x
+    evaluations) and systems completed per second of wall time."""
+    import numpy as np
+    import torch
+
+    from paper_1910_01235_amd import lattice as L
+    from paper_1910_01235_amd import mxe
+    from paper_1910_01235_amd import serve
+
+    systems = L.config4_requests(seed=seed, n_requests=n_requests)
+    params = dict(L.DEFAULT_PARAMS)
+    n_tot = sum(s.n for s in systems)
+    reqs = serve.poisson_requests(systems, n_steps=n_steps, rate=0.0)
+
+    # one at a time: a plan per request, in order (the plain path)
+    torch.cuda.synchronize()
+    _, one = serve.serve_one_at_a_time(L.DEFAULT_EAM, params, reqs, realtime=False)
+
+    # all requests in one batched plan
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = mxe.Plan(systems, L.DEFAULT_EAM, params)
+    st, out, ws = plan.state(systems), plan.out(), plan.workspace()
+    plan.run(st, out, ws, n_steps, use_graph=True)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    sc = plan.scalars(out)
+    evals_b = sc[:, mxe.S_TOTAL_EVALS]
+    site_evals = float(sum(s.n * e for s, e in zip(systems, evals_b)))
+    status_b = int(np.bitwise_or.reduce(sc[:, mxe.S_STATUS].astype(np.int64)))
+    del plan, st, out, ws
+    torch.cuda.empty_cache()
+    batched = dict(systems_per_s=len(systems) / wall_b, site_evals_per_s=site_evals / wall_b,
+                   wall_s=wall_b, status=status_b)
+
+    # served: Poisson arrivals at 0.8 x the batched capacity, continuous batching
+    per_site = serve.bytes_per_site(L.DEFAULT_EAM, params)
+    caps = serve.pool_capacities(24e9, per_site)
+    srv = serve.Server(L.DEFAULT_EAM, params, caps)
+    warm = serve.poisson_requests([L.vacancy_bulk(5, 1, 800.0, 0)], n_steps=1, rate=0.0)
+    srv.serve(warm, realtime=False)  # records the step graph
+    rate = 0.8 * batched["systems_per_s"]
+    reqs_p = serve.poisson_requests(systems, n_steps=n_steps, rate=rate, seed=seed)
+    res, rejected, st_s = srv.serve(reqs_p, realtime=True)
+    served = dict(arrival_rate_per_s=rate, systems_per_s=st_s["systems_per_s"],
+                  site_steps_per_s=st_s["site_steps_per_s"], p50_s=st_s["p50_s"], p99_s=st_s["p99_s"],
+                  rejected=len(rejected), slots=st_s["slots"], footprint_gb=st_s["footprint_bytes"] / 1e9,
+                  status=int(np.bitwise_or.reduce([r.status for r in res])) if res else 0)
+    del srv
+    torch.cuda.empty_cache()
+    return dict(requests=len(systems), sites=n_tot, steps_per_request=n_steps,
+                max_relax=params["max_relax"], batched=batched,
+                one_at_a_time=dict(systems_per_s=one["systems_per_s"], makespan_s=one["makespan_s"],
+                                   p50_s=one["p50_s"], p99_s=one["p99_s"]),
+                batched_vs_one_at_a_time=batched["systems_per_s"] / one["systems_per_s"],
+                served=served)
 
 
 def timed_run(plan, st, out, ws, steps, use_graph, profile):
@@ -110,9 +173,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=24576)
+    ap.add_argument("--cpu-sample", type=int, default=256000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the graph and FP32 legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the graph, FP32 and batched legs")
+    ap.add_argument("--batch-requests", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -215,6 +280,11 @@ def main():
                                     evals=ev32, status=int(sc_32[mxe.S_STATUS]),
                                     kernel_ms={k: v[0] for k, v in prof32.items()})
         log(f"fp32 leg: {wall_32:.3f} s")
+        del st32, out32, ws32, p32
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        result["many_systems"] = batched_legs(args.batch_requests, args.batch_steps)
+        log(f"batched/served legs: {time.perf_counter() - t0:.1f} s")
 
     if args.calib_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
