@@ -40,7 +40,7 @@ class _Eam(C.Structure):
     _fields_ = [("embed_c", C.c_double * 3), ("emit_b", C.c_double * 3),
                 ("pair_a", (C.c_double * 3) * 3), ("r_e", C.c_double * 2),
                 ("alpha", C.c_double * 2), ("gamma", C.c_double * 2),
-                ("r_s", C.c_double), ("r_c", C.c_double)]
+                ("r_s", C.c_double), ("r_c", C.c_double), ("quad_rule", C.c_int)]
 
 
 class _Box(C.Structure):
@@ -94,6 +94,7 @@ def make_eam(eam: dict) -> _Eam:
         e.gamma[c] = eam["gamma"][c]
     e.r_s = eam["r_s"]
     e.r_c = eam["r_c"]
+    e.quad_rule = int(eam.get("quad_rule", 0))
     return e
 
 
@@ -140,6 +141,25 @@ def pair_average(eam: dict, cls: int, rbar, s: float) -> np.ndarray:
     rb = np.ascontiguousarray(rbar, dtype=np.float64)
     out = np.zeros(14)
     lib().oref_pair_average(C.byref(e), C.c_int(cls), _dp(rb), C.c_double(s), _dp(out))
+    return out
+
+
+def stroud_nodes(sigma_i: float, sigma_j: float):
+    """Degree-3 rule of the pair: (12, 6) displacements (dq_i, dq_j) and 12 weights."""
+    off = np.zeros((12, 6))
+    w = np.zeros(12)
+    lib().oref_stroud_nodes(C.c_double(sigma_i), C.c_double(sigma_j), _dp(off), _dp(w))
+    return off, w
+
+
+def pair_moments(eam: dict, cls: int, rbar, sigma_i: float, sigma_j: float) -> np.ndarray:
+    """16 moments under eam["quad_rule"]: <phi>, grad<phi>(3), d<phi>/dsigma_i, <f>,
+    grad<f>(3), d<f>/dsigma_i, f0, grad f0(3), d<phi>/dsigma_j, d<f>/dsigma_j."""
+    e = make_eam(eam)
+    rb = np.ascontiguousarray(rbar, dtype=np.float64)
+    out = np.zeros(16)
+    lib().oref_pair_moments(C.byref(e), C.c_int(cls), _dp(rb), C.c_double(sigma_i),
+                            C.c_double(sigma_j), _dp(out))
     return out
 
 

@@ -193,6 +193,83 @@ void oref_pair_average(const oref_eam* e, int cls, const double rbar[3], double 
     }
 }
 
+/* Degree-3 rule of App. A, Eq. (QuadRule), for the N_q = 6 coordinates of a
+ * pair. In the scaled variables chi = (q - qbar)/(sqrt(2) sigma) the weight
+ * is exp(-|chi|^2); the M = 2 N_q nodes sit at +-r on each coordinate axis
+ * with r^2 = N_q/2, and each weight pi^(N_q/2)/(2 N_q) times the
+ * normalisation pi^(-N_q/2) is 1/(2 N_q). */
+void oref_stroud_nodes(double sigma_i, double sigma_j, double off[12][6], double w[12]) {
+    const int nq = 6;
+    const double r = sqrt(nq / 2.0);
+    int k = 0;
+    for (int axis = 0; axis < nq; ++axis)
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            for (int a = 0; a < nq; ++a) off[k][a] = 0.0;
+            double sig = axis < 3 ? sigma_i : sigma_j;
+            off[k][axis] = sqrt(2.0) * sig * (sgn * r);
+            w[k] = 1.0 / (2.0 * nq);
+            ++k;
+        }
+}
+
+static void pair_moments_stroud(const oref_eam* e, int cls, const double rbar[3], double si,
+                                double sj, double out[16]) {
+    double off[12][6], w[12];
+    oref_stroud_nodes(si, sj, off, w);
+    for (int m = 0; m < 16; ++m) out[m] = 0.0;
+    double re = e->r_e[cls], al = e->alpha[cls], ga = e->gamma[cls];
+    for (int k = 0; k < 12; ++k) {
+        /* d = (q_j + dq_j) - (q_i + dq_i); d d/dsigma_i = -dq_i/sigma_i, d d/dsigma_j = dq_j/sigma_j */
+        double d[3], r2 = 0.0, ddi = 0.0, ddj = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = rbar[a] + off[k][3 + a] - off[k][a];
+            r2 += d[a] * d[a];
+        }
+        for (int a = 0; a < 3; ++a) {
+            ddi += d[a] * (-off[k][a] / si);
+            ddj += d[a] * (off[k][3 + a] / sj);
+        }
+        double r = sqrt(r2);
+        if (r >= e->r_c || r == 0.0) continue;
+        double gp, dgp, gf, dgf;
+        oref_shape(e, r, re, al, &gp, &dgp);
+        oref_shape(e, r, re, ga, &gf, &dgf);
+        out[0] += w[k] * gp;
+        for (int a = 0; a < 3; ++a) out[1 + a] += w[k] * dgp * d[a] / r;
+        out[4] += w[k] * dgp * ddi / r;
+        out[14] += w[k] * dgp * ddj / r;
+        out[5] += w[k] * gf;
+        for (int a = 0; a < 3; ++a) out[6 + a] += w[k] * dgf * d[a] / r;
+        out[9] += w[k] * dgf * ddi / r;
+        out[15] += w[k] * dgf * ddj / r;
+    }
+    double r0 = sqrt(rbar[0] * rbar[0] + rbar[1] * rbar[1] + rbar[2] * rbar[2]);
+    if (r0 > 0.0) {
+        double g0, dg0;
+        oref_shape(e, r0, re, ga, &g0, &dg0);
+        out[10] = g0;
+        for (int a = 0; a < 3; ++a) out[11 + a] = dg0 * rbar[a] / r0;
+    }
+}
+
+void oref_pair_moments(const oref_eam* e, int cls, const double rbar[3], double si, double sj,
+                       double out[16]) {
+    if (e->quad_rule == 1) {
+        pair_moments_stroud(e, cls, rbar, si, sj, out);
+        return;
+    }
+    /* product rule: the average depends on s = sqrt(si^2 + sj^2) only, so
+     * d/dsigma_i = (sigma_i / s) d/ds */
+    double m[14];
+    double s = sqrt(si * si + sj * sj);
+    oref_pair_average(e, cls, rbar, s, m);
+    for (int k = 0; k < 14; ++k) out[k] = m[k];
+    out[4] = (si / s) * m[4];
+    out[9] = (si / s) * m[9];
+    out[14] = (sj / s) * m[4];
+    out[15] = (sj / s) * m[9];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry: minimum image and neighbour search.                            */
 /* ------------------------------------------------------------------------ */
@@ -372,7 +449,9 @@ typedef struct {
 } evalctx;
 
 /* Does some quadrature node of the pair reach inside r_c?  The farthest node
- * offset is s * |zeta| = 3 s, so pairs with |rbar| >= r_c + 3 s give zero. */
+ * of the product rule is 3 s from rbar, and that of the degree-3 rule
+ * sqrt(6) max(sigma_i, sigma_j) <= 3 s, so pairs with |rbar| >= r_c + 3 s
+ * give zero under either rule. */
 static int pair_active(const evalctx* c, int i, int j, double d[3], double* s, int* cls) {
     *cls = pair_class(c->type[i], c->type[j]);
     if (*cls < 0) return 0;
@@ -394,10 +473,10 @@ static int pass1_site(evalctx* c, int i) {
     double rb = 0.0, r0 = 0.0;
     for (int k = c->nb.start[i]; k < c->nb.start[i + 1]; ++k) {
         int j = c->nb.j[k];
-        double d[3], s, m[14];
+        double d[3], s, m[16];
         int cls;
         if (!pair_active(c, i, j, d, &s, &cls)) continue;
-        oref_pair_average(c->e, cls, d, s, m);
+        oref_pair_moments(c->e, cls, d, c->sigma[i], c->sigma[j], m);
         double bj = site_val(c->e->emit_b, c->type[j], c->x[j]);
         rb += bj * m[5];
         r0 += bj * m[10];
@@ -432,10 +511,10 @@ static void pass2_site(const evalctx* c, int i, double grad[4], double force[4],
     double mui = 0.0, epair = 0.0;
     for (int k = c->nb.start[i]; k < c->nb.start[i + 1]; ++k) {
         int j = c->nb.j[k];
-        double d[3], s, m[14];
+        double d[3], s, m[16];
         int cls;
         if (!pair_active(c, i, j, d, &s, &cls)) continue;
-        oref_pair_average(e, cls, d, s, m);
+        oref_pair_moments(e, cls, d, si, c->sigma[j], m);
         int tj = c->type[j];
         double xj = c->x[j];
         double aij = pair_amp(e, ti, xi, tj, xj);
@@ -451,8 +530,8 @@ static void pass2_site(const evalctx* c, int i, double grad[4], double force[4],
             g[a] -= aij * m[1 + a] + cA * m[6 + a] + cB * m[11 + a];
             gh[a] -= ahat * m[1 + a] + hA * m[6 + a] + hB * m[11 + a];
         }
-        g[3] += (si / s) * (aij * m[4] + cA * m[9]);
-        gh[3] += (si / s) * (ahat * m[4] + hA * m[9]);
+        g[3] += aij * m[4] + cA * m[9];
+        gh[3] += ahat * m[4] + hA * m[9];
         mui += dadx * m[0] + dbdx * (c->Atil[j] * m[5] + c->Btil[j] * m[10]);
         epair += 0.5 * aij * m[0];
     }

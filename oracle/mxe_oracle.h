@@ -27,6 +27,9 @@ typedef struct {
     double alpha[2];      /* phi shape exp(-alpha (r/r_e - 1)) * taper          */
     double gamma[2];      /* f shape exp(-gamma (r/r_e - 1)) * taper            */
     double r_s, r_c;      /* cosine taper from r_s to r_c                       */
+    int quad_rule;        /* phase-average rule: 0 = 27-node Gauss-Hermite product
+                           * rule on the pair's relative coordinate; 1 = the
+                           * degree-3 rule of App. A in the 6-D pair space     */
 } oref_eam;
 
 typedef struct {
@@ -63,6 +66,18 @@ void oref_quadrature(double zeta[27][3], double w[27]);
  * <f>, grad<f>(3), d<f>/ds, f0, grad f0 (3). */
 void oref_pair_average(const oref_eam* e, int cls, const double rbar[3], double s,
                        double out[14]);
+
+/* Degree-3 rule of App. A (Eq. QuadRule) for the 6-D coordinates of a pair
+ * (q_i, q_j): 12 nodes, off[k] = (dq_i, dq_j) displacements from the means,
+ * all weights 1/12. */
+void oref_stroud_nodes(double sigma_i, double sigma_j, double off[12][6], double w[12]);
+
+/* Pair moments under the rule selected by e->quad_rule, for rbar = qbar_j - qbar_i
+ * and widths sigma_i, sigma_j. out[16] = <phi>, grad<phi>(3), d<phi>/dsigma_i,
+ * <f>, grad<f>(3), d<f>/dsigma_i, f0, grad f0 (3), d<phi>/dsigma_j, d<f>/dsigma_j.
+ * Gradients are with respect to rbar. */
+void oref_pair_moments(const oref_eam* e, int cls, const double rbar[3], double sigma_i,
+                       double sigma_j, double out[16]);
 
 /* Radial shape and its derivative (taper included). */
 void oref_shape(const oref_eam* e, double r, double r_e, double a, double* g, double* dg);

@@ -124,8 +124,8 @@ def test_perfect_lattice_symmetry(sig):
     assert abs(out["F"] - out["e_site"].sum()) < 1e-9
 
 
-def _fd_errors(s, h=1e-5, nprobe=10, seed=0):
-    out = O.evaluate(EAM, s.box, s.periodic, s.T, s.q, s.sigma, s.x, s.type)
+def _fd_errors(s, h=1e-5, nprobe=10, seed=0, eam=EAM):
+    out = O.evaluate(eam, s.box, s.periodic, s.T, s.q, s.sigma, s.x, s.type)
     kT = KB * s.T
     rng = np.random.default_rng(seed)
     gmax = np.abs(out["grad"]).max()
@@ -141,7 +141,7 @@ def _fd_errors(s, h=1e-5, nprobe=10, seed=0):
                 q[i, a] += delta
             else:
                 sg[i] += delta
-            return O.free_energy(EAM, s.box, s.periodic, s.T, q, sg, s.x, s.type)
+            return O.free_energy(eam, s.box, s.periodic, s.T, q, sg, s.x, s.type)
 
         fd = (F(h) - F(-h)) / (2 * h)
         err_g = max(err_g, abs(fd - out["grad"][i, a]) / gmax)
@@ -156,7 +156,7 @@ def _fd_errors(s, h=1e-5, nprobe=10, seed=0):
             x[i] += delta
             xi = x[i]
             mix = kT * (xi * math.log(xi) + (1 - xi) * math.log(1 - xi))
-            return O.free_energy(EAM, s.box, s.periodic, s.T, s.q, s.sigma, x, s.type) - mix
+            return O.free_energy(eam, s.box, s.periodic, s.T, s.q, s.sigma, x, s.type) - mix
 
         fd = (Fm(h) - Fm(-h)) / (2 * h)
         err_mu = max(err_mu, abs(fd - out["mu"][i]) / mumax)
