@@ -282,6 +282,22 @@ def main():
         log(f"fp32 leg: {wall_32:.3f} s")
         del st32, out32, ws32, p32
         torch.cuda.empty_cache()
+        # the paper's own degree-3 rule (12 nodes in the pair's 6-D space)
+        result["degree3"] = {}
+        for prec in ("fp64", "fp32"):
+            eam3 = dict(w.eam, quad_rule=1)
+            p3 = mxe.Plan([s], eam3, w.params, precision=prec)
+            st3, out3, ws3 = p3.state([s]), p3.out(), p3.workspace()
+            p3.run(st3, out3, ws3, args.warmup, use_graph=True)
+            wall3, sc3, prof3 = timed_run(p3, st3, out3, ws3, args.steps, use_graph=False, profile=True)
+            ev3 = int(sc3[mxe.S_TOTAL_EVALS])
+            result["degree3"][prec] = dict(
+                value=n * ev3 / wall3, ms_per_step=wall3 / args.steps * 1e3, evals=ev3,
+                status=int(sc3[mxe.S_STATUS]),
+                kernel_ms_avg={k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof3.items()})
+            log(f"degree-3 {prec} leg: {wall3:.3f} s")
+            del st3, out3, ws3, p3
+            torch.cuda.empty_cache()
         t0 = time.perf_counter()
         result["many_systems"] = batched_legs(args.batch_requests, args.batch_steps)
         log(f"batched/served legs: {time.perf_counter() - t0:.1f} s")

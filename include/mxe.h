@@ -57,6 +57,9 @@ typedef enum {
 
 typedef enum { MXE_FP64 = 0, MXE_FP32_MIXED = 1 } mxe_precision;
 
+/* phase-average quadrature rule */
+typedef enum { MXE_QUAD_GH27 = 0, MXE_QUAD_DEGREE3 = 1 } mxe_quad_rule;
+
 /* Site types. Each site holds its mobile species with probability x and the
  * complement with 1 - x (Sec. 2, Eq. occupancy; App. B.2.1):
  *   HOST_VAC      atom A or vacancy        (x = fraction of A)
@@ -109,6 +112,12 @@ typedef struct {
      * (0 = 256; 64, 128, 256) */
     int gather_lanes;
     int pair_block;
+    /* phase-average rule (App. A): MXE_QUAD_GH27 (default) integrates the
+     * pair's relative coordinate with the 27-node Gauss-Hermite product rule;
+     * MXE_QUAD_DEGREE3 uses the 12-node degree-3 rule of Eq. (QuadRule) in
+     * the pair's 6-D coordinate space (each end displaced by +-sqrt(6) sigma
+     * along one axis, weights 1/12) */
+    int quad_rule;
 } mxe_params;
 
 typedef struct {

@@ -180,6 +180,8 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
         return fail(MXE_EINVAL, "gather_lanes must be 0, 8, 16, 32 or 64");
     if (p.pair_block != 0 && p.pair_block != 64 && p.pair_block != 128 && p.pair_block != 256)
         return fail(MXE_EINVAL, "pair_block must be 0, 64, 128 or 256");
+    if (p.quad_rule != MXE_QUAD_GH27 && p.quad_rule != MXE_QUAD_DEGREE3)
+        return fail(MXE_EINVAL, "quad_rule must be MXE_QUAD_GH27 (0) or MXE_QUAD_DEGREE3 (1)");
     if (!(p.sigma_min > 0) || !(p.sigma_cap > p.sigma_min) || !(p.skin > 0) || !(p.dt_safety > 0) ||
         !(p.r_bond > 0) || !(p.ftol >= 0) || !(p.fire_dt0 > 0) || !(p.fire_dtmax > 0))
         return fail(MXE_EINVAL, "bad sigma_min / sigma_cap / skin / dt_safety / r_bond / ftol / FIRE steps");
@@ -229,6 +231,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     m.dt_safety = p.dt_safety;
     m.gather_lanes = p.gather_lanes ? p.gather_lanes : 8;
     m.pair_block = p.pair_block ? p.pair_block : 256;
+    m.quad_rule = p.quad_rule;
 
     // largest list radius the cells must cover
     P->r_cap = eam->r_c + 3.0 * std::sqrt(2.0) * p.sigma_cap + p.skin;

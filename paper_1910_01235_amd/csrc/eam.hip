@@ -3,13 +3,16 @@
 // Phase averages (App. A): a pair term depends on q_j - q_i only; for two
 // independent Gaussian packets of per-axis widths sigma_i, sigma_j this is a
 // Gaussian of mean rbar = qbar_j - qbar_i and width s = sqrt(sigma_i^2 + sigma_j^2),
-// averaged here by the 27-node product Gauss-Hermite rule (per axis: nodes
-// 0, +-sqrt(3), weights 2/3, 1/6, 1/6). The Taylor form of the embedding
-// (App. B.2, Eq. F_taylor_mxe) needs the density at the mean positions as well.
+// averaged by the 27-node product Gauss-Hermite rule (per axis: nodes
+// 0, +-sqrt(3), weights 2/3, 1/6, 1/6). Alternatively the degree-3 rule of
+// App. A, Eq. (QuadRule), integrates the pair's six coordinates directly:
+// 12 nodes, each displacing one end by +-sqrt(6) sigma along one axis, all
+// weighted 1/12. The Taylor form of the embedding (App. B.2, Eq. F_taylor_mxe)
+// needs the density at the mean positions as well.
 //
 // The work is split so that each unordered pair's quadrature runs once:
-//   k_pair     one thread per pair (i < j): 27 nodes -> 14 moments; both radial
-//              shapes share each node's distance. Stored per pair as one force
+//   k_pair     one thread per pair (i < j): 27 (or 12 + centre) nodes -> 16
+//              moments; both radial shapes share each node's distance. Stored per pair as one force
 //              block (16 slots: a 128-byte line in FP64) and one density pair
 //              (<f>, f0), so a gather from either end reads whole lines.
 //   k_density  kLPS lanes per site, lanes over its neighbour row: gathers
@@ -137,9 +140,10 @@ __device__ inline void shapes(T r, T inv_re, T al, T ga, T r_s, T tw, T& gp, T& 
     dgf = ef * (dS - ga * inv_re * S);
 }
 
+// 27-node product rule on the relative coordinate (width s)
 template <typename T>
-__device__ inline void pair_moments(const Model& m, int cls, double rx, double ry, double rz,
-                                    double s, T out[kMom]) {
+__device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, double ry, double rz,
+                                         double s, T out[kFBlk]) {
     constexpr T kSqrt3 = T(1.7320508075688772935);
     const T inv_re = (T)m.inv_re[cls], al = (T)m.alpha[cls], ga = (T)m.gamma[cls];
     const T r_s = (T)m.r_s, tw = (T)m.taper_inv_w;
@@ -153,7 +157,7 @@ __device__ inline void pair_moments(const Model& m, int cls, double rx, double r
     const T Z2[3] = {Z[0] * Z[0], Z[1] * Z[1], Z[2] * Z[2]};
     constexpr T w1[3] = {T(1.0 / 6.0), T(2.0 / 3.0), T(1.0 / 6.0)};
 #pragma unroll
-    for (int k = 0; k < kMom; ++k) out[k] = T(0);
+    for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -198,6 +202,88 @@ __device__ inline void pair_moments(const Model& m, int cls, double rx, double r
     const T sinv = T(1) / (T)s;
     out[M_SPHI] *= sinv;
     out[M_SF] *= sinv;
+    // d/dsigma_e = (sigma_e / s) d/ds: divided by sigma_e both ends get (d/ds)/s
+    out[M_SPHI_HI] = out[M_SPHI];
+    out[M_SF_HI] = out[M_SF];
+}
+
+// One radial shape and its derivative at r < r_c.
+template <typename T>
+__device__ inline void one_shape(T r, T inv_re, T a, T r_s, T tw, T& g, T& dg) {
+    const T e = Math<T>::ex(-a * (r * inv_re - T(1)));
+    T S = T(1), dS = T(0);
+    if (r > r_s) {
+        T sn;
+        Math<T>::taper((r - r_s) * tw, S, sn);
+        dS = T(-0.5) * T(3.14159265358979323846) * tw * sn;
+    }
+    g = e * S;
+    dg = e * (dS - a * inv_re * S);
+}
+
+// Degree-3 rule of App. A in the pair's six coordinates. A node that moves the
+// lo end by -c h e_a or the hi end by +c h e_a (h = sqrt(6) sigma_end, c = +-1)
+// sits at d = rbar + c h e_a, and d.(dd/dsigma_end) = c sqrt(6) d_a.
+template <typename T>
+__device__ inline void pair_moments_d3(const Model& m, int cls, double rx, double ry, double rz,
+                                       double si, double sj, T out[kFBlk]) {
+    constexpr T kSqrt6 = T(2.4494897427831780982);
+    constexpr T W = T(1.0 / 12.0);
+    const T inv_re = (T)m.inv_re[cls], al = (T)m.alpha[cls], ga = (T)m.gamma[cls];
+    const T r_s = (T)m.r_s, tw = (T)m.taper_inv_w;
+    const T rc2 = (T)(m.r_c * m.r_c);
+    const T R[3] = {(T)rx, (T)ry, (T)rz};
+    const T R2[3] = {R[0] * R[0], R[1] * R[1], R[2] * R[2]};
+    const T other[3] = {R2[1] + R2[2], R2[0] + R2[2], R2[0] + R2[1]};
+#pragma unroll
+    for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
+    T ws[2][2] = {{T(0), T(0)}, {T(0), T(0)}};  // [end][shape]: sum c d_a g'/r
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const T h = kSqrt6 * (T)(e == 0 ? si : sj);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int c = -1; c <= 1; c += 2) {
+                const T da = R[a] + T(c) * h;
+                const T r2 = other[a] + da * da;
+                if (r2 < rc2 && r2 > T(0)) {
+                    const T rinv = Math<T>::rsq(r2);
+                    const T r = r2 * rinv;
+                    T gp, dgp, gf, dgf;
+                    shapes<T>(r, inv_re, al, ga, r_s, tw, gp, dgp, gf, dgf);
+                    const T cp = W * dgp * rinv, cf = W * dgf * rinv;
+                    out[M_PHI] += W * gp;
+                    out[M_F] += W * gf;
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const T db = b == a ? da : R[b];
+                        out[M_GPHI + b] += cp * db;
+                        out[M_GF + b] += cf * db;
+                    }
+                    ws[e][0] += cp * (T(c) * da);
+                    ws[e][1] += cf * (T(c) * da);
+                }
+            }
+        }
+    }
+    // (d<g>/dsigma_e) / sigma_e = sqrt(6) ws / sigma_e
+    const T fi = kSqrt6 / (T)si, fj = kSqrt6 / (T)sj;
+    out[M_SPHI] = ws[0][0] * fi;
+    out[M_SF] = ws[0][1] * fi;
+    out[M_SPHI_HI] = ws[1][0] * fj;
+    out[M_SF_HI] = ws[1][1] * fj;
+    const T r2c = other[0] + R2[0];
+    if (r2c < rc2 && r2c > T(0)) {  // the density at the mean positions
+        const T rinv = Math<T>::rsq(r2c);
+        T gf, dgf;
+        one_shape<T>(r2c * rinv, inv_re, ga, r_s, tw, gf, dgf);
+        const T g0 = dgf * rinv;
+        out[M_F0] = gf;
+        out[M_GF0 + 0] = g0 * R[0];
+        out[M_GF0 + 1] = g0 * R[1];
+        out[M_GF0 + 2] = g0 * R[2];
+    }
 }
 
 __device__ inline void min_image(const SysDesc& S, double& dx, double& dy, double& dz) {
@@ -215,7 +301,7 @@ struct alignas(16) Vec16 {
     T v[n];
 };
 
-template <typename T, int kBS>
+template <typename T, int kBS, int kRule>
 __global__ __launch_bounds__(kBS, 3) void k_pair(Dev d, Model m) {
     const Chunk ch = d.pchunks[blockIdx.x];
     const SysCtl& c = d.ctl[ch.sys];
@@ -235,8 +321,13 @@ __global__ __launch_bounds__(kBS, 3) void k_pair(Dev d, Model m) {
         T out[kFBlk];
 #pragma unroll
         for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
-        if (cls >= 0 && rx * rx + ry * ry + rz * rz < (m.r_c + 3.0 * s) * (m.r_c + 3.0 * s))
-            pair_moments<T>(m, cls, rx, ry, rz, s, out);
+        // a pair contributes iff some node lies inside r_c: the farthest node is
+        // 3 s from rbar under the product rule, sqrt(6) max(sigma) under degree 3
+        const double reach = kRule == MXE_QUAD_DEGREE3 ? 2.449489742783178 * fmax(si, sj) : 3.0 * s;
+        if (cls >= 0 && rx * rx + ry * ry + rz * rz < (m.r_c + reach) * (m.r_c + reach)) {
+            if (kRule == MXE_QUAD_DEGREE3) pair_moments_d3<T>(m, cls, rx, ry, rz, si, sj, out);
+            else pair_moments_gh27<T>(m, cls, rx, ry, rz, s, out);
+        }
 #pragma unroll
         for (int v = 0; v < per; ++v) {
             Vec16<T> b;
@@ -329,8 +420,8 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
 // B_j = c_j F~''(rho0_j)(rho_bar_j - rho0_j):
 //   -dF/dq_i / w_i = sum_j sign [ahat grad<phi> + (Ahat_i b_j + A_j bhat_i) grad<f>
 //                                + (Bhat_i b_j + B_j bhat_i) grad f0]
-//   -dF/dsigma_i / w_i = -sigma_i sum_j [ahat <phi>_s + (Ahat_i b_j + A_j bhat_i) <f>_s] / s
-//                       + 3 kT / sigma_i
+//   -dF/dsigma_i / w_i = -sigma_i sum_j [ahat <phi>_si + (Ahat_i b_j + A_j bhat_i) <f>_si]
+//                       + 3 kT / sigma_i,   <g>_si = (d<g>/dsigma_i) / sigma_i
 //   mu_i = sum_j da_ij/dx_i <phi> + db_i/dx_i sum_j (A_j <f> + B_j f0)
 //          + dc_i/dx_i G_i - 3 kT dw_i/dx_i ln sigma_i
 // Force gather layout: kLPS lanes per site; inside them, groups of four lanes
@@ -399,21 +490,22 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
                 fx += c * m1;
                 fy += c * m2;
                 fz += c * m3;
-            } else if (q == 1) {  // <phi>_s / s, <f>, grad <f> (x, y)
-                fsg += ahat * m0;
+            } else if (q == 1) {  // lo-end width term of <phi>, <f>, grad <f> (x, y)
+                if (sg > 0.0) fsg += ahat * m0;
                 mu += db_i * Aj * m1;
                 const double c = sg * hA;
                 fx += c * m2;
                 fy += c * m3;
-            } else if (q == 2) {  // grad <f> (z), <f>_s / s, f0, grad f0 (x)
+            } else if (q == 2) {  // grad <f> (z), lo-end width term of <f>, f0, grad f0 (x)
                 fz += sg * hA * m0;
-                fsg += hA * m1;
+                if (sg > 0.0) fsg += hA * m1;
                 mu += db_i * Bj * m2;
                 fx += sg * hB * m3;
-            } else {              // grad f0 (y, z)
+            } else {              // grad f0 (y, z), hi-end width terms of <phi>, <f>
                 const double c = sg * hB;
                 fy += c * m0;
                 fz += c * m1;
+                if (sg < 0.0) fsg += ahat * m2 + hA * m3;
             }
         }
         fx = group_sum<kLPS>(fx);
@@ -481,13 +573,19 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
     }
 }
 
+template <typename T, int kRule>
+void launch_pair_r(const Dev& d, const Model& m, int bs, hipStream_t s) {
+    switch (bs) {
+        case 64: k_pair<T, 64, kRule><<<d.n_pchunks, 64, 0, s>>>(d, m); break;
+        case 128: k_pair<T, 128, kRule><<<d.n_pchunks, 128, 0, s>>>(d, m); break;
+        default: k_pair<T, 256, kRule><<<d.n_pchunks, 256, 0, s>>>(d, m); break;
+    }
+}
+
 template <typename T>
 void launch_pair_t(const Dev& d, const Model& m, int bs, hipStream_t s) {
-    switch (bs) {
-        case 64: k_pair<T, 64><<<d.n_pchunks, 64, 0, s>>>(d, m); break;
-        case 128: k_pair<T, 128><<<d.n_pchunks, 128, 0, s>>>(d, m); break;
-        default: k_pair<T, 256><<<d.n_pchunks, 256, 0, s>>>(d, m); break;
-    }
+    if (m.quad_rule == MXE_QUAD_DEGREE3) launch_pair_r<T, MXE_QUAD_DEGREE3>(d, m, bs, s);
+    else launch_pair_r<T, MXE_QUAD_GH27>(d, m, bs, s);
 }
 
 template <typename T>

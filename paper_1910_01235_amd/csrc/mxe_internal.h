@@ -8,8 +8,7 @@
 
 namespace mxe {
 
-constexpr int kMom = 14;            // moments computed per pair (see pair kernel)
-constexpr int kFBlk = 16;           // force block per pair: 14 moments + 2 pad = one 128-byte line (FP64)
+constexpr int kFBlk = 16;           // force block per pair: 16 moments = one 128-byte line (FP64)
 constexpr int kSRec = 8;            // per-site record: A~, B~, b, pair amplitude against A, B, S, 2 pad
 constexpr int kChunk = 256;         // sites per site-chunk; block size of per-site kernels
 constexpr int kPairChunk = 4096;    // pair slots per pair-chunk
@@ -17,12 +16,15 @@ constexpr int kNPart = 8;           // partial sums per site-chunk
 constexpr int kWave = 64;
 constexpr double kBoltzmannEv = 8.617333262e-5;  // eV/K
 
-// moment slots of a pair, computed at rbar = q_hi - q_lo; this is also the
-// layout of the pair's force block (slots 14, 15 unused)
+// moment slots of a pair (lo, hi) = (i, j), computed at rbar = q_hi - q_lo;
+// this is also the layout of the pair's force block. Width derivatives are
+// stored divided by the width of their end: (d<g>/dsigma_lo)/sigma_lo and
+// (d<g>/dsigma_hi)/sigma_hi; under the product rule both equal (d<g>/ds)/s.
 enum {
-    M_PHI = 0, M_GPHI = 1, M_SPHI = 4,   // <phi>, grad <phi> (3), (d<phi>/ds)/s
-    M_F = 5, M_GF = 6, M_SF = 9,         // <f>, grad <f> (3), (d<f>/ds)/s
-    M_F0 = 10, M_GF0 = 11                // f(|rbar|), grad f(|rbar|) (3)
+    M_PHI = 0, M_GPHI = 1, M_SPHI = 4,   // <phi>, grad <phi> (3), lo-end width term
+    M_F = 5, M_GF = 6, M_SF = 9,         // <f>, grad <f> (3), lo-end width term
+    M_F0 = 10, M_GF0 = 11,               // f(|rbar|), grad f(|rbar|) (3)
+    M_SPHI_HI = 14, M_SF_HI = 15         // hi-end width terms of <phi>, <f>
 };
 
 // partial-sum slots of a site-chunk
@@ -72,6 +74,7 @@ struct Model {
     int nmin, max_relax;
     double sigma_min, sigma_cap, skin, r_bond, kin_c, dt_safety;
     int gather_lanes, pair_block;  // launch shapes (tuned per workload)
+    int quad_rule;                 // MXE_QUAD_GH27 or MXE_QUAD_DEGREE3
 };
 
 // Every device pointer the kernels use.

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmxe.so")
 
 FP64, FP32_MIXED = 0, 1
+QUAD_GH27, QUAD_DEGREE3 = 0, 1
 NSCALARS = 16
 S_F, S_FMAX, S_DT, S_TIME, S_SUMX, S_UPDATES, S_CONVERGED, S_EVALS, S_STATUS, S_REBUILDS, \
     S_TOTAL_EVALS, S_PAIRS, S_PAIR_EVALS = range(13)
@@ -47,7 +48,7 @@ class Params(C.Structure):
                 ("fire_nmin", C.c_int), ("sigma_min", C.c_double), ("sigma_cap", C.c_double),
                 ("skin", C.c_double), ("r_bond", C.c_double), ("k_max", C.c_int),
                 ("bond_max", C.c_int), ("precision", C.c_int), ("gather_lanes", C.c_int),
-                ("pair_block", C.c_int)]
+                ("pair_block", C.c_int), ("quad_rule", C.c_int)]
 
 
 class System(C.Structure):
@@ -134,7 +135,7 @@ _PARAM_MAP = dict(nu0="nu0", Qm="Qm", kin_c="kin_c", dt_safety="dt_safety",
                   alpha0="fire_alpha0", finc="fire_finc", fdec="fire_fdec", falpha="fire_falpha",
                   nmin="fire_nmin", sigma_min="sigma_min", r_bond="r_bond", sigma_cap="sigma_cap",
                   skin="skin", k_max="k_max", bond_max="bond_max", gather_lanes="gather_lanes",
-                  pair_block="pair_block")
+                  pair_block="pair_block", quad_rule="quad_rule")
 
 
 def make_params(params: dict, precision: str = "fp64", **over) -> Params:
@@ -220,6 +221,8 @@ class Plan:
                 arr[k].box[a] = float(s.box[a])
                 arr[k].periodic[a] = int(bool(s.periodic[a]))
             arr[k].T = float(s.T)
+        if "quad_rule" in eam and "quad_rule" not in over:
+            over = dict(over, quad_rule=int(eam["quad_rule"]))
         self.params = make_params(params, precision, **over)
         self.eam = make_eam(eam)
         self.n_systems = len(systems)
