@@ -43,9 +43,12 @@ class _Eam(C.Structure):
                 ("r_s", C.c_double), ("r_c", C.c_double), ("quad_rule", C.c_int)]
 
 
+RES_NONE, RES_FIX_X, RES_FIX_MU = 0, 1, 2
+
+
 class _Box(C.Structure):
     _fields_ = [("n", C.c_int), ("box", C.c_double * 3), ("periodic", C.c_int * 3),
-                ("T", C.c_double)]
+                ("T", C.c_double), ("res", C.POINTER(C.c_int8)), ("res_val", C.POINTER(C.c_double))]
 
 
 class _Params(C.Structure):
@@ -98,13 +101,22 @@ def make_eam(eam: dict) -> _Eam:
     return e
 
 
-def make_box(n, box, periodic, T) -> _Box:
+def make_box(n, box, periodic, T, res=None, res_val=None) -> _Box:
+    """System description; res / res_val: optional per-site reservoir kinds and held values."""
     b = _Box()
     b.n = int(n)
     for a in range(3):
         b.box[a] = float(box[a])
         b.periodic[a] = int(bool(periodic[a]))
     b.T = float(T)
+    b._keep = []
+    if res is not None:
+        r = np.ascontiguousarray(res, dtype=np.int8)
+        v = np.ascontiguousarray(res_val, dtype=np.float64)
+        assert r.shape == (n,) and v.shape == (n,)
+        b._keep += [r, v]
+        b.res = _bp(r)
+        b.res_val = _dp(v)
     return b
 
 
@@ -173,11 +185,11 @@ def _state(q, sigma, x, type_):
     return q, sigma, x, type_, n
 
 
-def evaluate(eam, box, periodic, T, q, sigma, x, type_):
+def evaluate(eam, box, periodic, T, q, sigma, x, type_, res=None, res_val=None):
     """Full evaluation. Returns a dict of numpy arrays and the total F."""
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T)
+    b = make_box(n, box, periodic, T, res, res_val)
     out = {k: np.zeros(n) for k in ("rho_bar", "rho0", "mu", "e_site")}
     out["grad"] = np.zeros((n, 4))
     out["force"] = np.zeros((n, 4))
@@ -191,10 +203,10 @@ def evaluate(eam, box, periodic, T, q, sigma, x, type_):
     return out
 
 
-def free_energy(eam, box, periodic, T, q, sigma, x, type_) -> float:
+def free_energy(eam, box, periodic, T, q, sigma, x, type_, res=None, res_val=None) -> float:
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T)
+    b = make_box(n, box, periodic, T, res, res_val)
     F = C.c_double()
     st = lib().oref_evaluate(C.byref(e), C.byref(b), _dp(q), _dp(sigma), _dp(x), _bp(type_),
                              None, None, None, None, None, None, C.byref(F))
@@ -203,12 +215,12 @@ def free_energy(eam, box, periodic, T, q, sigma, x, type_) -> float:
     return F.value
 
 
-def evaluate_sites(eam, box, periodic, T, q, sigma, x, type_, sel):
+def evaluate_sites(eam, box, periodic, T, q, sigma, x, type_, sel, res=None, res_val=None):
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     sel = np.ascontiguousarray(sel, dtype=np.int32)
     m = sel.shape[0]
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T)
+    b = make_box(n, box, periodic, T, res, res_val)
     out = {k: np.zeros(m) for k in ("rho_bar", "rho0", "mu", "e_site")}
     out["force"] = np.zeros((m, 4))
     st = lib().oref_evaluate_sites(C.byref(e), C.byref(b), _dp(q), _dp(sigma), _dp(x),
@@ -247,14 +259,14 @@ def bonds(box, periodic, q, type_, r_bond, bmax=16):
     return nb, bl
 
 
-def master_rates(params, box, periodic, T, x, type_, mu, nbond, bond_list):
+def master_rates(params, box, periodic, T, x, type_, mu, nbond, bond_list, res=None, res_val=None):
     x = np.ascontiguousarray(x, dtype=np.float64)
     mu = np.ascontiguousarray(mu, dtype=np.float64)
     type_ = np.ascontiguousarray(type_, dtype=np.int8)
     nbond = np.ascontiguousarray(nbond, dtype=np.int32)
     bond_list = np.ascontiguousarray(bond_list, dtype=np.int32)
     n = x.shape[0]
-    b = make_box(n, box, periodic, T)
+    b = make_box(n, box, periodic, T, res, res_val)
     p = make_params(params)
     dxdt = np.zeros(n)
     dt = C.c_double()
@@ -264,13 +276,35 @@ def master_rates(params, box, periodic, T, x, type_, mu, nbond, bond_list):
     return dxdt, dt.value
 
 
-def relax(eam, params, box, periodic, T, q, sigma, x, type_):
+def master_step(params, box, periodic, T, x, type_, mu, nbond, bond_list, dt_in=0.0, res=None,
+                res_val=None):
+    """One Euler step of x with held reservoir sites; returns (x, dxdt, dt, uptake)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).copy()
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    type_ = np.ascontiguousarray(type_, dtype=np.int8)
+    nbond = np.ascontiguousarray(nbond, dtype=np.int32)
+    bond_list = np.ascontiguousarray(bond_list, dtype=np.int32)
+    n = x.shape[0]
+    b = make_box(n, box, periodic, T, res, res_val)
+    p = make_params(params)
+    dxdt = np.zeros(n)
+    dt = C.c_double()
+    up = C.c_double(0.0)
+    st = lib().oref_master_step(C.byref(b), C.byref(p), _dp(x), _bp(type_), _dp(mu),
+                                C.c_int(bond_list.shape[1]), _ip(nbond), _ip(bond_list),
+                                C.c_double(dt_in), _dp(dxdt), C.byref(dt), C.byref(up))
+    if st != OK:
+        raise RuntimeError(f"oracle master_step failed: {st}")
+    return x, dxdt, dt.value, up.value
+
+
+def relax(eam, params, box, periodic, T, q, sigma, x, type_, res=None, res_val=None):
     """FIRE relaxation; returns (q, sigma, info dict) with the last evaluation's outputs."""
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     q = q.copy()
     sigma = sigma.copy()
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T)
+    b = make_box(n, box, periodic, T, res, res_val)
     p = make_params(params)
     force = np.zeros((n, 4))
     mu = np.zeros(n)
@@ -288,22 +322,23 @@ def relax(eam, params, box, periodic, T, q, sigma, x, type_):
                           force=force, mu=mu, e_site=es, F=F.value, fmax=fmax.value)
 
 
-def run(eam, params, box, periodic, T, n_steps, q, sigma, x, type_, t0=0.0):
+def run(eam, params, box, periodic, T, n_steps, q, sigma, x, type_, t0=0.0, res=None, res_val=None):
     """Staggered relax + master-equation run. Returns final state and per-step records."""
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     q = q.copy()
     sigma = sigma.copy()
     x = x.copy()
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T)
+    b = make_box(n, box, periodic, T, res, res_val)
     p = make_params(params)
     mu = np.zeros(n)
     dxdt = np.zeros(n)
     t = C.c_double(t0)
-    rec = np.zeros((n_steps, 6))
+    rec = np.zeros((n_steps, 7))
     st = lib().oref_run(C.byref(e), C.byref(b), C.byref(p), C.c_int(n_steps), _dp(q),
                         _dp(sigma), _dp(x), _bp(type_), _dp(mu), _dp(dxdt), C.byref(t), _dp(rec))
     if st != OK:
         raise RuntimeError(f"oracle run failed: {st}")
     return dict(q=q, sigma=sigma, x=x, mu=mu, dxdt=dxdt, t=t.value, updates=rec[:, 0],
-                converged=rec[:, 1], F=rec[:, 2], fmax=rec[:, 3], dt=rec[:, 4], sum_x=rec[:, 5])
+                converged=rec[:, 1], F=rec[:, 2], fmax=rec[:, 3], dt=rec[:, 4], sum_x=rec[:, 5],
+                uptake=rec[:, 6])

@@ -609,6 +609,13 @@ static void ctx_free(evalctx* c) {
     free(c->need1);
 }
 
+/* setchemicalpotential (Sec. 4): after the forces, mu of a held mobile site
+ * is replaced by the held value */
+static double held_mu(const oref_box* b, const int8_t* type, int i, double mu) {
+    if (b->res && b->res[i] == OREF_RES_FIX_MU && is_mobile(type[i])) return b->res_val[i];
+    return mu;
+}
+
 int oref_evaluate(const oref_eam* e, const oref_box* b, const double* q, const double* sigma,
                   const double* x, const int8_t* type, double* rho_bar, double* rho0,
                   double* grad, double* force, double* mu, double* e_site, double* F_out) {
@@ -634,7 +641,7 @@ int oref_evaluate(const oref_eam* e, const oref_box* b, const double* q, const d
             for (int a = 0; a < 4; ++a) grad[4 * i + a] = g4[a];
         if (force)
             for (int a = 0; a < 4; ++a) force[4 * i + a] = f4[a];
-        if (mu) mu[i] = m;
+        if (mu) mu[i] = held_mu(b, type, i, m);
     }
     double F = 0.0;
     for (int i = 0; i < n; ++i) F += es[i];
@@ -682,7 +689,7 @@ int oref_evaluate_sites(const oref_eam* e, const oref_box* b, const double* q,
         pass2_site(&c, i, NULL, f4, &m, &es);
         if (force)
             for (int a = 0; a < 4; ++a) force[4 * s + a] = f4[a];
-        if (mu) mu[s] = m;
+        if (mu) mu[s] = held_mu(b, type, i, m);
         if (e_site) e_site[s] = es;
         if (rho_bar) rho_bar[s] = c.rho_bar[i];
         if (rho0) rho0[s] = c.rho0[i];
@@ -749,6 +756,30 @@ int oref_master_rates(const oref_box* b, const oref_params* p, const double* x,
         if (rin > rmax) rmax = rin;
     }
     *dt = rmax > 0.0 ? p->dt_safety / rmax : 0.0;
+    return OREF_OK;
+}
+
+/* Forward-Euler step (Sec. 4) followed by setatomicfraction: the mass
+ * transport update comes first, then held sites are reset (Algorithm 1 calls
+ * the transport fix at the start of the step and the fraction fix after it). */
+int oref_master_step(const oref_box* b, const oref_params* p, double* x, const int8_t* type,
+                     const double* mu, int bmax, const int* nbond, const int* bonds,
+                     double dt_in, double* dxdt, double* dt, double* uptake) {
+    double h;
+    int st = oref_master_rates(b, p, x, type, mu, bmax, nbond, bonds, dxdt, &h);
+    if (st != OREF_OK) return st;
+    if (dt_in > 0.0) h = dt_in;
+    double taken = 0.0;
+    for (int i = 0; i < b->n; ++i) {
+        if (!is_mobile(type[i])) continue;
+        x[i] += h * dxdt[i];
+        if (b->res && b->res[i] == OREF_RES_FIX_X) {
+            taken += x[i] - b->res_val[i];
+            x[i] = b->res_val[i];
+        }
+    }
+    if (uptake) *uptake += taken;
+    *dt = h;
     return OREF_OK;
 }
 
@@ -847,6 +878,10 @@ int oref_run(const oref_eam* e, const oref_box* b, const oref_params* p, int n_s
         return st;
     }
     double t = t_out ? *t_out : 0.0;
+    double uptake = 0.0;
+    if (b->res)
+        for (int i = 0; i < n; ++i)
+            if (b->res[i] == OREF_RES_FIX_X && is_mobile(type[i])) x[i] = b->res_val[i];
     for (int s = 0; s < n_steps; ++s) {
         double F, fmax, dt;
         int conv, nev;
@@ -855,20 +890,18 @@ int oref_run(const oref_eam* e, const oref_box* b, const oref_params* p, int n_s
             st = upd;
             break;
         }
-        oref_master_rates(b, p, x, type, mu, bmax, nbond, bonds, dxdt, &dt);
+        oref_master_step(b, p, x, type, mu, bmax, nbond, bonds, 0.0, dxdt, &dt, &uptake);
         double sx = 0.0;
-        for (int i = 0; i < n; ++i) {
-            if (is_mobile(type[i])) x[i] += dt * dxdt[i];
-            sx += x[i];
-        }
+        for (int i = 0; i < n; ++i) sx += x[i];
         t += dt;
         if (rec) {
-            rec[6 * s + 0] = upd;
-            rec[6 * s + 1] = conv;
-            rec[6 * s + 2] = F;
-            rec[6 * s + 3] = fmax;
-            rec[6 * s + 4] = dt;
-            rec[6 * s + 5] = sx;
+            rec[7 * s + 0] = upd;
+            rec[7 * s + 1] = conv;
+            rec[7 * s + 2] = F;
+            rec[7 * s + 3] = fmax;
+            rec[7 * s + 4] = dt;
+            rec[7 * s + 5] = sx;
+            rec[7 * s + 6] = uptake;
         }
     }
     if (t_out) *t_out = t;

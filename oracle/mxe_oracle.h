@@ -32,11 +32,19 @@ typedef struct {
                            * degree-3 rule of App. A in the 6-D pair space     */
 } oref_eam;
 
+/* reservoir kinds of a site (Sec. 4: the setatomicfraction and
+ * setchemicalpotential commands hold x, or mu, of a group at a given value) */
+#define OREF_RES_NONE 0
+#define OREF_RES_FIX_X 1
+#define OREF_RES_FIX_MU 2
+
 typedef struct {
     int n;
     double box[3];
     int periodic[3];
-    double T;             /* uniform temperature, K */
+    double T;             /* temperature, K */
+    const int8_t* res;    /* per-site reservoir kind (OREF_RES_*), or NULL    */
+    const double* res_val;/* the held x or mu of reservoir sites, or NULL     */
 } oref_box;
 
 typedef struct {
@@ -82,7 +90,8 @@ void oref_pair_moments(const oref_eam* e, int cls, const double rbar[3], double 
 /* Radial shape and its derivative (taper included). */
 void oref_shape(const oref_eam* e, double r, double r_e, double a, double* g, double* dg);
 
-/* Full evaluation. Any output pointer may be NULL.
+/* Full evaluation. Any output pointer may be NULL. On mobile sites marked
+ * OREF_RES_FIX_MU the returned mu is the held value (applied after the forces).
  * grad:  raw gradient dF/d(qx,qy,qz,sigma), [n][4]
  * force: occupancy-normalised force -dF/dy / w, [n][4]
  * Returns OREF_OK or an error code; *F_out = total free energy. */
@@ -112,6 +121,15 @@ int oref_master_rates(const oref_box* b, const oref_params* p, const double* x,
                       const int8_t* type, const double* mu, int bmax, const int* nbond,
                       const int* bonds, double* dxdt, double* dt);
 
+/* One forward-Euler step of x: rates as above, x += dt dxdt on mobile sites,
+ * then mobile sites marked OREF_RES_FIX_X are reset to their held value; the
+ * matter they took up in the step (x after the update minus the held value)
+ * is added to *uptake. dt_in > 0 replaces the stable step. Returns the step
+ * used in *dt. */
+int oref_master_step(const oref_box* b, const oref_params* p, double* x, const int8_t* type,
+                     const double* mu, int bmax, const int* nbond, const int* bonds,
+                     double dt_in, double* dxdt, double* dt, double* uptake);
+
 /* FIRE relaxation of (q, sigma) at fixed x. q and sigma are updated in place.
  * Outputs of the last evaluation go to the given arrays. Returns the number
  * of FIRE updates made; *converged = 1 if max|f| <= ftol was reached. */
@@ -120,8 +138,10 @@ int oref_relax(const oref_eam* e, const oref_box* b, const oref_params* p, doubl
                double* mu, double* e_site, double* F_out, double* fmax_out,
                int* converged, int* n_evals);
 
-/* Staggered run: n_steps x (relax, master-equation Euler step).
- * rec[n_steps][6] = relax updates, converged, F, max|f|, dt, sum x (after step). */
+/* Staggered run: n_steps x (relax, master-equation Euler step). Mobile
+ * OREF_RES_FIX_X sites are set to their held value before the first step.
+ * rec[n_steps][7] = relax updates, converged, F, max|f|, dt, sum x (after
+ * step), reservoir uptake accumulated since the start of the run. */
 int oref_run(const oref_eam* e, const oref_box* b, const oref_params* p, int n_steps,
              double* q, double* sigma, double* x, const int8_t* type, double* mu,
              double* dxdt, double* t_out, double* rec);
