@@ -127,7 +127,21 @@ typedef struct {
     double T;            /* temperature (K), uniform over the system           */
 } mxe_system;
 
-/* Device buffers, SoA FP64, concatenated over systems. */
+/* Reservoir kinds of a mobile site (Sec. 4: the setatomicfraction and
+ * setchemicalpotential commands hold the molar fraction, or the chemical
+ * potential, of a group of sites at a given value). */
+typedef enum {
+    MXE_RES_NONE = 0,
+    MXE_RES_FIX_X = 1,   /* x is reset to the held value after every Euler step
+                          * and at the start of every call; the matter the site
+                          * took up in a step is added to MXE_S_RESERVOIR      */
+    MXE_RES_FIX_MU = 2   /* mu is replaced by the held value after the forces  */
+} mxe_reservoir;
+
+/* Device buffers, SoA FP64, concatenated over systems. reservoir and
+ * res_value are optional (both NULL: no reservoir sites); when given, one
+ * int8 kind (mxe_reservoir) and one held value per site. Reservoir kinds
+ * on HOST_FIXED sites are ignored. */
 typedef struct {
     double* qx;
     double* qy;
@@ -135,6 +149,8 @@ typedef struct {
     double* sigma;
     double* x;
     const int8_t* type;
+    const int8_t* reservoir;
+    const double* res_value;
 } mxe_state;
 
 /* Outputs. fx..fsigma are the occupancy-normalised forces -dF/dy / w_i that
@@ -167,7 +183,9 @@ typedef enum {
     MXE_S_REBUILDS = 9,   /* neighbour-list builds during the call              */
     MXE_S_TOTAL_EVALS = 10, /* evaluations during the call                       */
     MXE_S_PAIRS = 11,     /* pairs in the current neighbour list                */
-    MXE_S_PAIR_EVALS = 12, /* pair quadratures (27 nodes each) during the call  */
+    MXE_S_PAIR_EVALS = 12, /* pair quadratures during the call                  */
+    MXE_S_RESERVOIR = 13, /* matter taken up by held-x sites; in/out, accumulated
+                           * like MXE_S_TIME: sum x + this stays constant      */
     MXE_NSCALARS = 16
 } mxe_scalar;
 

@@ -362,6 +362,8 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
                           out->e_site, out->scalars};
     for (const void* q : need)
         if (!q) return fail(MXE_EINVAL, "a state or output pointer is NULL");
+    if ((st->reservoir == nullptr) != (st->res_value == nullptr))
+        return fail(MXE_EINVAL, "reservoir and res_value must both be given or both be NULL");
     char* w = (char*)ws;
     Dev& D = *d;
     std::memset(&D, 0, sizeof(D));
@@ -371,6 +373,8 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.sigma = st->sigma;
     D.x = st->x;
     D.type = st->type;
+    D.res = st->reservoir;
+    D.res_val = st->res_value;
     D.fx = out->fx;
     D.fy = out->fy;
     D.fz = out->fz;
@@ -575,7 +579,8 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
         HIP_OK(hipGetLastError());
         return MXE_OK;
     }
-    std::vector<const void*> key = {st->qx, st->qy, st->qz, st->sigma, st->x, st->type, out->fx, out->fy,
+    std::vector<const void*> key = {st->qx, st->qy, st->qz, st->sigma, st->x, st->type,
+                                    st->reservoir, st->res_value, out->fx, out->fy,
                                     out->fz, out->fsigma, out->mu, out->dxdt, out->rho_bar, out->rho0,
                                     out->e_site, out->scalars, ws};
     if (!P->graph || key != P->graph_key) {

@@ -522,6 +522,7 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
             double mui = 0.0, mix = 0.0;
             if (mob_i) {
                 mui = mu + mixdx(m.c4, ti) * Gi - 3.0 * kT * (part_i ? 1.0 : 0.0) * lns;
+                if (held(d, i, ti, MXE_RES_FIX_MU)) mui = d.res_val[i];  // held after the forces
                 if (xi > 0.0) mix += xi * log(xi);
                 if (xi < 1.0) mix += (1.0 - xi) * log(1.0 - xi);
                 mix *= kT;

@@ -28,7 +28,7 @@ enum {
 };
 
 // partial-sum slots of a site-chunk
-enum { P_E = 0, P_FMAX = 1, P_FV = 2, P_FF = 3, P_VV = 4, P_SUMX = 5, P_RATE = 6 };
+enum { P_E = 0, P_FMAX = 1, P_FV = 2, P_FF = 3, P_VV = 4, P_SUMX = 5, P_RATE = 6, P_RES = 7 };
 
 struct SysDesc {
     int64_t site_off, n_sites;
@@ -82,6 +82,8 @@ struct Dev {
     // state
     double *qx, *qy, *qz, *sigma, *x;
     const int8_t* type;
+    const int8_t* res;     // reservoir kind per site, or null
+    const double* res_val; // held x or mu per site, or null
     // outputs
     double *fx, *fy, *fz, *fs, *mu, *dxdt, *rho_bar, *rho0, *e_site, *scalars;
     // workspace
@@ -120,6 +122,10 @@ __host__ __device__ inline int occ_sp1(int t) { return t == MXE_SITE_ALLOY ? 1 :
 __host__ __device__ inline int occ_sp0(int t) { return t == MXE_SITE_ALLOY ? 0 : 3; }
 __host__ __device__ inline double occ_p1(int t, double x) { return t == MXE_SITE_HOST_FIXED ? 1.0 : x; }
 __host__ __device__ inline bool occ_mobile(int t) { return t != MXE_SITE_HOST_FIXED; }
+// is mobile site i (of type t) a reservoir site of the given kind?
+__device__ inline bool held(const Dev& d, int i, int t, int kind) {
+    return d.res != nullptr && d.res[i] == kind && occ_mobile(t);
+}
 __host__ __device__ inline bool occ_partial(int t) {  // vibrating fraction w = x
     return t == MXE_SITE_HOST_VAC || t == MXE_SITE_INTERSTITIAL;
 }

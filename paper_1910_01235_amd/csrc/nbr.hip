@@ -118,7 +118,11 @@ __global__ __launch_bounds__(kChunk) void k_site_init(Dev d, Model m) {
     int st = 0;
     if (i < ch.end) {
         sg = d.sigma[i];
-        const double xi = d.x[i];
+        double xi = d.x[i];
+        if (held(d, i, d.type[i], MXE_RES_FIX_X)) {  // held fraction (set at the call start)
+            xi = d.res_val[i];
+            d.x[i] = xi;
+        }
         if (!(sg > 0.0) || !isfinite(sg)) st |= MXE_STAT_NONFINITE;
         if (sg > m.sigma_cap) st |= MXE_STAT_SIGMA_CAP;
         if (!isfinite(xi) || xi < -1e-12 || xi > 1.0 + 1e-12) st |= MXE_STAT_X_RANGE;

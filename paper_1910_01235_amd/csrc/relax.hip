@@ -245,35 +245,50 @@ __global__ __launch_bounds__(kChunk) void k_mstep_ctl(Dev d, Model m, double dt_
     out[MXE_S_TIME] += dt;
 }
 
+// Forward-Euler update of x (Sec. 4), then held-x sites are reset to their
+// value; the matter they took up in the step goes to the reservoir account.
 __global__ __launch_bounds__(kChunk) void k_euler(Dev d, Model m) {
     __shared__ double lds[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
     const int i = ch.start + threadIdx.x;
-    double xi = 0.0;
+    double xi = 0.0, taken = 0.0;
     if (i < ch.end) {
         xi = d.x[i];
-        if (occ_mobile(d.type[i])) {
+        const int ti = d.type[i];
+        if (occ_mobile(ti)) {
             xi += d.ctl[ch.sys].dt_master * d.dxdt[i];
+            if (held(d, i, ti, MXE_RES_FIX_X)) {
+                taken = xi - d.res_val[i];
+                xi = d.res_val[i];
+            }
             d.x[i] = xi;
-            d.emit[i] = mixval(m.b4, d.type[i], xi);
+            d.emit[i] = mixval(m.b4, ti, xi);
             if (!(xi >= -1e-12 && xi <= 1.0 + 1e-12)) atomicOr(&d.ctl[ch.sys].status, MXE_STAT_X_RANGE);
         }
     }
     const double t = block_sum(xi, lds);
-    if (threadIdx.x == 0) d.part[(int64_t)blockIdx.x * kNPart + P_SUMX] = t;
+    const double r = d.res != nullptr ? block_sum(taken, lds) : 0.0;
+    if (threadIdx.x == 0) {
+        d.part[(int64_t)blockIdx.x * kNPart + P_SUMX] = t;
+        d.part[(int64_t)blockIdx.x * kNPart + P_RES] = r;
+    }
 }
 
 __global__ __launch_bounds__(kChunk) void k_estep_ctl(Dev d) {
     __shared__ double lds[kChunk / kWave];
     const int s = blockIdx.x;
     const SysDesc& S = d.sys[s];
-    double t = 0.0;
-    for (int k = threadIdx.x; k < S.n_chunks; k += blockDim.x)
+    double t = 0.0, r = 0.0;
+    for (int k = threadIdx.x; k < S.n_chunks; k += blockDim.x) {
         t += d.part[(int64_t)(S.chunk_first + k) * kNPart + P_SUMX];
+        r += d.part[(int64_t)(S.chunk_first + k) * kNPart + P_RES];
+    }
     t = block_sum(t, lds);
+    r = d.res != nullptr ? block_sum(r, lds) : 0.0;
     if (threadIdx.x != 0) return;
     double* out = sc(d, s);
     out[MXE_S_SUMX] = t;
+    out[MXE_S_RESERVOIR] += r;
     out[MXE_S_STATUS] = (double)d.ctl[s].status;
 }
 

@@ -17,9 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libmxe.so")
 
 FP64, FP32_MIXED = 0, 1
 QUAD_GH27, QUAD_DEGREE3 = 0, 1
+RES_NONE, RES_FIX_X, RES_FIX_MU = 0, 1, 2
 NSCALARS = 16
 S_F, S_FMAX, S_DT, S_TIME, S_SUMX, S_UPDATES, S_CONVERGED, S_EVALS, S_STATUS, S_REBUILDS, \
-    S_TOTAL_EVALS, S_PAIRS, S_PAIR_EVALS = range(13)
+    S_TOTAL_EVALS, S_PAIRS, S_PAIR_EVALS, S_RESERVOIR = range(14)
 K_PAIR, K_DENSITY, K_FORCE, K_BUILD, K_FIRE, K_MASTER = range(6)
 KERNEL_FAMILIES = ["pair", "density", "force", "build", "fire", "master"]
 STAT_NONFINITE, STAT_X_RANGE, STAT_RHO, STAT_SIGMA_MIN, STAT_KMAX, _STAT_RESERVED, STAT_PAIRS, \
@@ -58,7 +59,8 @@ class System(C.Structure):
 
 class State(C.Structure):
     _fields_ = [("qx", C.c_void_p), ("qy", C.c_void_p), ("qz", C.c_void_p),
-                ("sigma", C.c_void_p), ("x", C.c_void_p), ("type", C.c_void_p)]
+                ("sigma", C.c_void_p), ("x", C.c_void_p), ("type", C.c_void_p),
+                ("reservoir", C.c_void_p), ("res_value", C.c_void_p)]
 
 
 class Out(C.Structure):
@@ -171,10 +173,14 @@ class DeviceState:
     sigma: "torch.Tensor"
     x: "torch.Tensor"
     type: "torch.Tensor"
+    reservoir: "torch.Tensor" = None   # int8 kinds (RES_*), optional
+    res_value: "torch.Tensor" = None   # held x or mu, FP64, optional
 
     def abi(self) -> State:
+        opt = lambda t: t.data_ptr() if t is not None else None
         return State(self.qx.data_ptr(), self.qy.data_ptr(), self.qz.data_ptr(),
-                     self.sigma.data_ptr(), self.x.data_ptr(), self.type.data_ptr())
+                     self.sigma.data_ptr(), self.x.data_ptr(), self.type.data_ptr(),
+                     opt(self.reservoir), opt(self.res_value))
 
     def q(self):
         import torch
