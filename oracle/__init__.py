@@ -48,7 +48,8 @@ RES_NONE, RES_FIX_X, RES_FIX_MU = 0, 1, 2
 
 class _Box(C.Structure):
     _fields_ = [("n", C.c_int), ("box", C.c_double * 3), ("periodic", C.c_int * 3),
-                ("T", C.c_double), ("res", C.POINTER(C.c_int8)), ("res_val", C.POINTER(C.c_double))]
+                ("T", C.c_double), ("res", C.POINTER(C.c_int8)), ("res_val", C.POINTER(C.c_double)),
+                ("T_site", C.POINTER(C.c_double))]
 
 
 class _Params(C.Structure):
@@ -101,8 +102,9 @@ def make_eam(eam: dict) -> _Eam:
     return e
 
 
-def make_box(n, box, periodic, T, res=None, res_val=None) -> _Box:
-    """System description; res / res_val: optional per-site reservoir kinds and held values."""
+def make_box(n, box, periodic, T, res=None, res_val=None, T_site=None) -> _Box:
+    """System description; res / res_val: optional per-site reservoir kinds and held values;
+    T_site: optional per-site temperatures (T is then the reference temperature)."""
     b = _Box()
     b.n = int(n)
     for a in range(3):
@@ -117,6 +119,11 @@ def make_box(n, box, periodic, T, res=None, res_val=None) -> _Box:
         b._keep += [r, v]
         b.res = _bp(r)
         b.res_val = _dp(v)
+    if T_site is not None:
+        t = np.ascontiguousarray(T_site, dtype=np.float64)
+        assert t.shape == (n,)
+        b._keep.append(t)
+        b.T_site = _dp(t)
     return b
 
 
@@ -185,11 +192,11 @@ def _state(q, sigma, x, type_):
     return q, sigma, x, type_, n
 
 
-def evaluate(eam, box, periodic, T, q, sigma, x, type_, res=None, res_val=None):
+def evaluate(eam, box, periodic, T, q, sigma, x, type_, res=None, res_val=None, T_site=None):
     """Full evaluation. Returns a dict of numpy arrays and the total F."""
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T, res, res_val)
+    b = make_box(n, box, periodic, T, res, res_val, T_site)
     out = {k: np.zeros(n) for k in ("rho_bar", "rho0", "mu", "e_site")}
     out["grad"] = np.zeros((n, 4))
     out["force"] = np.zeros((n, 4))
@@ -203,10 +210,10 @@ def evaluate(eam, box, periodic, T, q, sigma, x, type_, res=None, res_val=None):
     return out
 
 
-def free_energy(eam, box, periodic, T, q, sigma, x, type_, res=None, res_val=None) -> float:
+def free_energy(eam, box, periodic, T, q, sigma, x, type_, res=None, res_val=None, T_site=None) -> float:
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T, res, res_val)
+    b = make_box(n, box, periodic, T, res, res_val, T_site)
     F = C.c_double()
     st = lib().oref_evaluate(C.byref(e), C.byref(b), _dp(q), _dp(sigma), _dp(x), _bp(type_),
                              None, None, None, None, None, None, C.byref(F))
@@ -215,12 +222,12 @@ def free_energy(eam, box, periodic, T, q, sigma, x, type_, res=None, res_val=Non
     return F.value
 
 
-def evaluate_sites(eam, box, periodic, T, q, sigma, x, type_, sel, res=None, res_val=None):
+def evaluate_sites(eam, box, periodic, T, q, sigma, x, type_, sel, res=None, res_val=None, T_site=None):
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     sel = np.ascontiguousarray(sel, dtype=np.int32)
     m = sel.shape[0]
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T, res, res_val)
+    b = make_box(n, box, periodic, T, res, res_val, T_site)
     out = {k: np.zeros(m) for k in ("rho_bar", "rho0", "mu", "e_site")}
     out["force"] = np.zeros((m, 4))
     st = lib().oref_evaluate_sites(C.byref(e), C.byref(b), _dp(q), _dp(sigma), _dp(x),
@@ -259,14 +266,14 @@ def bonds(box, periodic, q, type_, r_bond, bmax=16):
     return nb, bl
 
 
-def master_rates(params, box, periodic, T, x, type_, mu, nbond, bond_list, res=None, res_val=None):
+def master_rates(params, box, periodic, T, x, type_, mu, nbond, bond_list, res=None, res_val=None, T_site=None):
     x = np.ascontiguousarray(x, dtype=np.float64)
     mu = np.ascontiguousarray(mu, dtype=np.float64)
     type_ = np.ascontiguousarray(type_, dtype=np.int8)
     nbond = np.ascontiguousarray(nbond, dtype=np.int32)
     bond_list = np.ascontiguousarray(bond_list, dtype=np.int32)
     n = x.shape[0]
-    b = make_box(n, box, periodic, T, res, res_val)
+    b = make_box(n, box, periodic, T, res, res_val, T_site)
     p = make_params(params)
     dxdt = np.zeros(n)
     dt = C.c_double()
@@ -277,7 +284,7 @@ def master_rates(params, box, periodic, T, x, type_, mu, nbond, bond_list, res=N
 
 
 def master_step(params, box, periodic, T, x, type_, mu, nbond, bond_list, dt_in=0.0, res=None,
-                res_val=None):
+                res_val=None, T_site=None):
     """One Euler step of x with held reservoir sites; returns (x, dxdt, dt, uptake)."""
     x = np.ascontiguousarray(x, dtype=np.float64).copy()
     mu = np.ascontiguousarray(mu, dtype=np.float64)
@@ -285,7 +292,7 @@ def master_step(params, box, periodic, T, x, type_, mu, nbond, bond_list, dt_in=
     nbond = np.ascontiguousarray(nbond, dtype=np.int32)
     bond_list = np.ascontiguousarray(bond_list, dtype=np.int32)
     n = x.shape[0]
-    b = make_box(n, box, periodic, T, res, res_val)
+    b = make_box(n, box, periodic, T, res, res_val, T_site)
     p = make_params(params)
     dxdt = np.zeros(n)
     dt = C.c_double()
@@ -298,13 +305,13 @@ def master_step(params, box, periodic, T, x, type_, mu, nbond, bond_list, dt_in=
     return x, dxdt, dt.value, up.value
 
 
-def relax(eam, params, box, periodic, T, q, sigma, x, type_, res=None, res_val=None):
+def relax(eam, params, box, periodic, T, q, sigma, x, type_, res=None, res_val=None, T_site=None):
     """FIRE relaxation; returns (q, sigma, info dict) with the last evaluation's outputs."""
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     q = q.copy()
     sigma = sigma.copy()
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T, res, res_val)
+    b = make_box(n, box, periodic, T, res, res_val, T_site)
     p = make_params(params)
     force = np.zeros((n, 4))
     mu = np.zeros(n)
@@ -322,14 +329,14 @@ def relax(eam, params, box, periodic, T, q, sigma, x, type_, res=None, res_val=N
                           force=force, mu=mu, e_site=es, F=F.value, fmax=fmax.value)
 
 
-def run(eam, params, box, periodic, T, n_steps, q, sigma, x, type_, t0=0.0, res=None, res_val=None):
+def run(eam, params, box, periodic, T, n_steps, q, sigma, x, type_, t0=0.0, res=None, res_val=None, T_site=None):
     """Staggered relax + master-equation run. Returns final state and per-step records."""
     q, sigma, x, type_, n = _state(q, sigma, x, type_)
     q = q.copy()
     sigma = sigma.copy()
     x = x.copy()
     e = make_eam(eam)
-    b = make_box(n, box, periodic, T, res, res_val)
+    b = make_box(n, box, periodic, T, res, res_val, T_site)
     p = make_params(params)
     mu = np.zeros(n)
     dxdt = np.zeros(n)

@@ -442,7 +442,8 @@ typedef struct {
     const double *q, *sigma, *x;
     const int8_t* type;
     csr nb;
-    double kT;
+    double kT;            /* k_B T of the reference temperature */
+    const double* T_site; /* per-site temperatures or NULL */
     /* pass-1 results */
     double *rho_bar, *rho0, *G, *Atil, *Btil, *Ahat, *Bhat;
     char* need1; /* pass 1 required for this site */
@@ -463,6 +464,12 @@ static int pair_active(const evalctx* c, int i, int j, double d[3], double* s, i
 
 static int has_embedding(const oref_eam* e, int t) {
     return sp_val(e->embed_c, sp1_of(t)) != 0.0 || sp_val(e->embed_c, sp0_of(t)) != 0.0;
+}
+
+/* Weight of site i's energy share in k_B T times the free entropy of
+ * Eq. (Grand-Canonical-Free-Energy): beta_i / beta = T / T_i (1 at uniform T). */
+static double theta_of(const evalctx* c, int i) {
+    return c->T_site ? c->b->T / c->T_site[i] : 1.0;
 }
 
 /* pass 1: rho_bar_i = sum_j b_j <f_ij>, rho0_i = sum_j b_j f(|rbar_ij|);
@@ -494,10 +501,12 @@ static int pass1_site(evalctx* c, int i) {
     c->G[i] = F0 + F1 * (rb - r0);
     double ci = site_val(c->e->embed_c, t, c->x[i]);
     double ch = site_hat(c->e->embed_c, t, c->x[i]);
-    c->Atil[i] = ci * F1;
-    c->Btil[i] = ci * F2 * (rb - r0);
-    c->Ahat[i] = ch * F1;
-    c->Bhat[i] = ch * F2 * (rb - r0);
+    /* the embedding share c_i G_i enters with weight theta_i */
+    double th = theta_of(c, i);
+    c->Atil[i] = th * ci * F1;
+    c->Btil[i] = th * ci * F2 * (rb - r0);
+    c->Ahat[i] = th * ch * F1;
+    c->Bhat[i] = th * ch * F2 * (rb - r0);
     return OREF_OK;
 }
 
@@ -526,13 +535,15 @@ static void pass2_site(const evalctx* c, int i, double grad[4], double force[4],
         double cB = c->Btil[i] * bj + c->Btil[j] * bi;
         double hA = c->Ahat[i] * bj + c->Atil[j] * bhat;
         double hB = c->Bhat[i] * bj + c->Btil[j] * bhat;
+        /* the pair term sits half in each end's share: weight (theta_i + theta_j)/2 */
+        double tij = 0.5 * (theta_of(c, i) + theta_of(c, j));
         for (int a = 0; a < 3; ++a) {
-            g[a] -= aij * m[1 + a] + cA * m[6 + a] + cB * m[11 + a];
-            gh[a] -= ahat * m[1 + a] + hA * m[6 + a] + hB * m[11 + a];
+            g[a] -= tij * aij * m[1 + a] + cA * m[6 + a] + cB * m[11 + a];
+            gh[a] -= tij * ahat * m[1 + a] + hA * m[6 + a] + hB * m[11 + a];
         }
-        g[3] += aij * m[4] + cA * m[9];
-        gh[3] += ahat * m[4] + hA * m[9];
-        mui += dadx * m[0] + dbdx * (c->Atil[j] * m[5] + c->Btil[j] * m[10]);
+        g[3] += tij * aij * m[4] + cA * m[9];
+        gh[3] += tij * ahat * m[4] + hA * m[9];
+        mui += tij * dadx * m[0] + dbdx * (c->Atil[j] * m[5] + c->Btil[j] * m[10]);
         epair += 0.5 * aij * m[0];
     }
     /* vibrational part: -3 kT w ln sigma (Eq. Grand-Canonical-Free-Energy with
@@ -542,8 +553,11 @@ static void pass2_site(const evalctx* c, int i, double grad[4], double force[4],
     gh[3] -= 3.0 * c->kT / si;
     /* mu_i = d(F - E_mix)/dx_i (reading: the mixing entropy enters through the
      * x(1-x) prefactors of the kinetic law) */
+    /* mu_i = gamma_i / beta_i: the x_i-derivative of the functional divided by theta_i */
+    double thi = theta_of(c, i);
     if (is_mobile(ti)) {
-        mui += site_dval(e->embed_c, ti) * c->G[i] - 3.0 * c->kT * dw_of(ti) * log(si);
+        mui += thi * site_dval(e->embed_c, ti) * c->G[i] - 3.0 * c->kT * dw_of(ti) * log(si);
+        mui /= thi;
     } else {
         mui = 0.0;
     }
@@ -559,7 +573,7 @@ static void pass2_site(const evalctx* c, int i, double grad[4], double force[4],
     if (force)
         for (int a = 0; a < 4; ++a) force[a] = -gh[a];
     if (mu) *mu = mui;
-    if (esite) *esite = epair + ci * c->G[i] - 3.0 * c->kT * wi * log(si) + mix;
+    if (esite) *esite = thi * (epair + ci * c->G[i]) - 3.0 * c->kT * wi * log(si) + mix;
 }
 
 static double max_sigma(const double* sigma, int n) {
@@ -579,6 +593,10 @@ static int ctx_init(evalctx* c, const oref_eam* e, const oref_box* b, const doub
     c->x = x;
     c->type = type;
     c->kT = KB_EV * b->T;
+    c->T_site = b->T_site;
+    if (b->T_site)
+        for (int i = 0; i < b->n; ++i)
+            if (!(b->T_site[i] > 0.0)) return OREF_EINVAL;
     for (int i = 0; i < b->n; ++i)
         if (!(sigma[i] > 0.0)) return OREF_EINVAL;
     double radius = e->r_c + 3.0 * sqrt(2.0) * max_sigma(sigma, b->n) + 1e-6;
@@ -741,7 +759,24 @@ int oref_master_rates(const oref_box* b, const oref_params* p, const double* x,
     double rmax = 0.0;
     for (int i = 0; i < b->n; ++i) {
         double acc = 0.0, rout = 0.0, rin = 0.0;
-        if (is_mobile(type[i])) {
+        if (is_mobile(type[i]) && b->T_site) {
+            /* site temperatures (reading): a hop a -> b has attempt rate
+             * D_a = nu0 e^{-beta_a Qm} and driving factor e^{c beta_a (mu_a - mu_b)},
+             * both at the source site, so each hop has one rate in both
+             * equations and matter is conserved */
+            double bi = 1.0 / (KB_EV * b->T_site[i]);
+            double Di = p->nu0 * exp(-bi * p->Qm);
+            for (int k = 0; k < nbond[i]; ++k) {
+                int j = bonds[(size_t)i * bmax + k];
+                double bj = 1.0 / (KB_EV * b->T_site[j]);
+                double Dj = p->nu0 * exp(-bj * p->Qm);
+                double in = Dj * exp(p->kin_c * bj * (mu[j] - mu[i]));
+                double out = Di * exp(p->kin_c * bi * (mu[i] - mu[j]));
+                acc += x[j] * (1.0 - x[i]) * in - x[i] * (1.0 - x[j]) * out;
+                rout += (1.0 - x[j]) * out;
+                rin += x[j] * in;
+            }
+        } else if (is_mobile(type[i])) {
             for (int k = 0; k < nbond[i]; ++k) {
                 int j = bonds[(size_t)i * bmax + k];
                 double in = exp(cb * (mu[j] - mu[i]));

@@ -42,9 +42,16 @@ typedef struct {
     int n;
     double box[3];
     int periodic[3];
-    double T;             /* temperature, K */
+    double T;             /* temperature, K (the reference when T_site is set) */
     const int8_t* res;    /* per-site reservoir kind (OREF_RES_*), or NULL    */
     const double* res_val;/* the held x or mu of reservoir sites, or NULL     */
+    const double* T_site; /* per-site temperature T_i (K), or NULL = uniform T.
+                           * The relaxed functional is k_B T times the mean-field
+                           * free entropy of Eq. (Grand-Canonical-Free-Energy),
+                           * whose energy shares carry beta_i: each site's share
+                           * is weighted by theta_i = T / T_i; mu_i = gamma_i /
+                           * beta_i; each hop of the kinetic law runs at its
+                           * source site's temperature.                      */
 } oref_box;
 
 typedef struct {
