@@ -151,6 +151,14 @@ typedef struct {
     const int8_t* type;
     const int8_t* reservoir;
     const double* res_value;
+    /* optional per-site temperatures T_i (K), NULL = the system's T. Sec. 2
+     * gives every site its own beta_i: the relaxation then minimises k_B T
+     * (T = the system's reference temperature) times the mean-field free
+     * entropy of Eq. (Grand-Canonical-Free-Energy), whose energy shares carry
+     * beta_i (weight T / T_i); mu_i = gamma_i / beta_i; each hop of the
+     * kinetic law (Eqs. MassTransport, attempt_freq_mass) runs at its source
+     * site's temperature, so matter stays conserved. */
+    const double* T_site;
 } mxe_state;
 
 /* Outputs. fx..fsigma are the occupancy-normalised forces -dF/dy / w_i that
@@ -195,7 +203,7 @@ typedef enum {
     MXE_STAT_RHO = 4,         /* rho0 <= 0 on a site with an embedding        */
     MXE_STAT_SIGMA_MIN = 8,   /* a width was clamped at sigma_min (warning)   */
     MXE_STAT_KMAX = 16,       /* neighbour row overflow: results invalid      */
-    MXE_STAT_RESERVED = 32,   /* unused                                        */
+    MXE_STAT_TEMP = 32,       /* a site temperature is not positive and finite */
     MXE_STAT_PAIRS = 64,      /* pair buffer overflow: results invalid        */
     MXE_STAT_BONDS = 128,     /* bond row overflow: results invalid           */
     MXE_STAT_SIGMA_CAP = 256  /* a width exceeded sigma_cap: results invalid  */

@@ -97,6 +97,7 @@ void bind_slot(mxe_plan* P, int s, const mxe_system& ms) {
         ncell *= nc;
     }
     d.n_cells = ms.n_sites > 0 ? ncell : 0;
+    d.T = ms.T;
     d.kT = kBoltzmannEv * ms.T;
     d.beta = 1.0 / d.kT;
     d.D = P->p.nu0 * std::exp(-d.beta * P->p.Qm);
@@ -229,6 +230,8 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     m.r_bond = p.r_bond;
     m.kin_c = p.kin_c;
     m.dt_safety = p.dt_safety;
+    m.nu0 = p.nu0;
+    m.Qm = p.Qm;
     m.gather_lanes = p.gather_lanes ? p.gather_lanes : 8;
     m.pair_block = p.pair_block ? p.pair_block : 256;
     m.quad_rule = p.quad_rule;
@@ -375,6 +378,7 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.type = st->type;
     D.res = st->reservoir;
     D.res_val = st->res_value;
+    D.T_site = st->T_site;
     D.fx = out->fx;
     D.fy = out->fy;
     D.fz = out->fz;
@@ -580,7 +584,7 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
         return MXE_OK;
     }
     std::vector<const void*> key = {st->qx, st->qy, st->qz, st->sigma, st->x, st->type,
-                                    st->reservoir, st->res_value, out->fx, out->fy,
+                                    st->reservoir, st->res_value, st->T_site, out->fx, out->fy,
                                     out->fz, out->fsigma, out->mu, out->dxdt, out->rho_bar, out->rho0,
                                     out->e_site, out->scalars, ws};
     if (!P->graph || key != P->graph_key) {

@@ -380,6 +380,8 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
             const double xi = d.x[i];
             d.rho_bar[i] = rb;
             d.rho0[i] = r0;
+            // the embedding share c_i G_i carries the site's weight theta_i = T / T_i
+            const double th = theta_at(d, d.sys[ch.sys], i);
             double G = 0.0, A = 0.0, B = 0.0;
             const bool embeds = m.c4[occ_sp1(ti)] != 0.0 || m.c4[occ_sp0(ti)] != 0.0;
             if (embeds) {
@@ -389,8 +391,8 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
                     const double F1 = -0.5 / sq, F2 = 0.25 / (sq * r0);
                     const double ch_i = mixhat(m.c4, ti, xi);
                     G = -sq + F1 * (rb - r0);
-                    A = ch_i * F1;
-                    B = ch_i * F2 * (rb - r0);
+                    A = th * ch_i * F1;
+                    B = th * ch_i * F2 * (rb - r0);
                 } else {
                     atomicOr(&d.ctl[ch.sys].status, MXE_STAT_RHO);
                 }
@@ -399,7 +401,8 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
             d.Ahat[i] = A;
             d.Bhat[i] = B;
             // record read by the force gather of the neighbours: A~ = w A^, B~ = w B^,
-            // the emission and the pair amplitude against a partner of species A, B, S
+            // the emission, the pair amplitude against a partner of species A, B, S
+            // and the site's weight theta
             const double w = occ_partial(ti) ? xi : 1.0;
             const double p1 = occ_p1(ti, xi);
             const int s1 = occ_sp1(ti), s0 = occ_sp0(ti);
@@ -408,7 +411,7 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
             R[1] = w * B;
             R[2] = d.emit[i];
             for (int k = 0; k < 3; ++k) R[3 + k] = p1 * m.a4[k][s1] + (1.0 - p1) * m.a4[k][s0];
-            R[6] = 0.0;
+            R[6] = th;
             R[7] = 0.0;
         }
     }
@@ -439,6 +442,7 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
     if (d.ctl[sys].done) return;
     const SysDesc& S = d.sys[sys];
     const double kT = S.kT;
+    const bool site_T = d.T_site != nullptr;
     const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
     const int q = sub % kQ, es = sub / kQ;  // quarter of the block; entry slot
     const Vec16<T>* fblk = (const Vec16<T>*)d.fblk;
@@ -455,6 +459,7 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
         const int i1 = occ_sp1(ti), i0 = occ_sp0(ti);
         const double bhat_i = mixhat(m.b4, ti, xi), db_i = mixdx(m.b4, ti);
         const bool part_i = occ_partial(ti), mob_i = occ_mobile(ti);
+        const double th_i = theta_at(d, S, i);
         const int cnt = d.nbr_cnt[i];
         const int* row = d.nbr + (int64_t)i * K;
         const int* prow = d.pid + (int64_t)i * K;
@@ -477,8 +482,10 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
             const double a1 = ampA[i1];
             const double a0 = i0 < 3 ? ampA[i0] : 0.0;
             const double aij = pi1 * a1 + (1.0 - pi1) * a0;
-            const double ahat = part_i ? a1 : aij;
-            const double dadx = mob_i ? a1 - a0 : 0.0;
+            // the pair term sits half in each end's share: weight (theta_i + theta_j) / 2
+            const double tij = site_T ? 0.5 * (th_i + R[3].x) : 1.0;
+            const double ahat = tij * (part_i ? a1 : aij);
+            const double dadx = mob_i ? tij * (a1 - a0) : 0.0;
             const double hA = Ahi * bj + Aj * bhat_i;
             const double hB = Bhi * bj + Bj * bhat_i;
             const double sg = j > i ? 1.0 : -1.0;
@@ -521,13 +528,14 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
             const double wi = part_i ? xi : 1.0;
             double mui = 0.0, mix = 0.0;
             if (mob_i) {
-                mui = mu + mixdx(m.c4, ti) * Gi - 3.0 * kT * (part_i ? 1.0 : 0.0) * lns;
+                // mu_i = gamma_i / beta_i: the x_i-derivative divided by theta_i
+                mui = (mu + th_i * mixdx(m.c4, ti) * Gi - 3.0 * kT * (part_i ? 1.0 : 0.0) * lns) / th_i;
                 if (held(d, i, ti, MXE_RES_FIX_MU)) mui = d.res_val[i];  // held after the forces
                 if (xi > 0.0) mix += xi * log(xi);
                 if (xi < 1.0) mix += (1.0 - xi) * log(1.0 - xi);
                 mix *= kT;
             }
-            const double ei = 0.5 * ep + mixval(m.c4, ti, xi) * Gi - 3.0 * kT * wi * lns + mix;
+            const double ei = th_i * (0.5 * ep + mixval(m.c4, ti, xi) * Gi) - 3.0 * kT * wi * lns + mix;
             d.fx[i] = fx;
             d.fy[i] = fy;
             d.fz[i] = fz;

@@ -38,7 +38,7 @@ struct SysDesc {
     double cell_w[3];
     int nc[3];
     int periodic[3];
-    double kT, beta, D;
+    double T, kT, beta, D;  // reference temperature and its derived constants
     int chunk_first, n_chunks;
     int force_build;  // rebuild lists and bonds at the start of the call
     int pad;
@@ -72,7 +72,7 @@ struct Model {
     double r_s, r_c, taper_inv_w;
     double ftol, dt0, dtmax, alpha0, finc, fdec, falpha;
     int nmin, max_relax;
-    double sigma_min, sigma_cap, skin, r_bond, kin_c, dt_safety;
+    double sigma_min, sigma_cap, skin, r_bond, kin_c, dt_safety, nu0, Qm;
     int gather_lanes, pair_block;  // launch shapes (tuned per workload)
     int quad_rule;                 // MXE_QUAD_GH27 or MXE_QUAD_DEGREE3
 };
@@ -84,6 +84,7 @@ struct Dev {
     const int8_t* type;
     const int8_t* res;     // reservoir kind per site, or null
     const double* res_val; // held x or mu per site, or null
+    const double* T_site;  // per-site temperature, or null (uniform)
     // outputs
     double *fx, *fy, *fz, *fs, *mu, *dxdt, *rho_bar, *rho0, *e_site, *scalars;
     // workspace
@@ -122,6 +123,11 @@ __host__ __device__ inline int occ_sp1(int t) { return t == MXE_SITE_ALLOY ? 1 :
 __host__ __device__ inline int occ_sp0(int t) { return t == MXE_SITE_ALLOY ? 0 : 3; }
 __host__ __device__ inline double occ_p1(int t, double x) { return t == MXE_SITE_HOST_FIXED ? 1.0 : x; }
 __host__ __device__ inline bool occ_mobile(int t) { return t != MXE_SITE_HOST_FIXED; }
+// weight of site i's energy share, T / T_i (1 at uniform temperature)
+__device__ inline double theta_at(const Dev& d, const SysDesc& S, int i) {
+    return d.T_site != nullptr ? S.T / d.T_site[i] : 1.0;
+}
+
 // is mobile site i (of type t) a reservoir site of the given kind?
 __device__ inline bool held(const Dev& d, int i, int t, int kind) {
     return d.res != nullptr && d.res[i] == kind && occ_mobile(t);

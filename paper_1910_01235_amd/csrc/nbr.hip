@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kChunk) void k_site_init(Dev d, Model m) {
         if (sg > m.sigma_cap) st |= MXE_STAT_SIGMA_CAP;
         if (!isfinite(xi) || xi < -1e-12 || xi > 1.0 + 1e-12) st |= MXE_STAT_X_RANGE;
         if (!isfinite(d.qx[i]) || !isfinite(d.qy[i]) || !isfinite(d.qz[i])) st |= MXE_STAT_NONFINITE;
+        if (d.T_site != nullptr && !(d.T_site[i] > 0.0 && isfinite(d.T_site[i]))) st |= MXE_STAT_TEMP;
         if (!(sg > 0.0)) sg = 0.0;
         d.emit[i] = mixval(m.b4, d.type[i], xi);
     }

@@ -202,7 +202,28 @@ __global__ __launch_bounds__(kChunk) void k_flux(Dev d, Model m) {
     if (i < ch.end) {
         double acc = 0.0, rout = 0.0, rin = 0.0;
         const int ti = d.type[i];
-        if (occ_mobile(ti)) {
+        if (occ_mobile(ti) && d.T_site != nullptr) {
+            // site temperatures: a hop a -> b has attempt rate nu0 e^{-beta_a Qm} and
+            // driving factor e^{c beta_a (mu_a - mu_b)}, both at its source site, so
+            // the pair's net flux is the same seen from either end
+            const int nb = d.nbond[i];
+            const int* row = d.bond + (int64_t)i * d.bond_max;
+            for (int b = 0; b < nb; ++b) {
+                const int j = row[b];
+                const bool i_lo = i < j;
+                const int lo = i_lo ? i : j, hi = i_lo ? j : i;
+                const double xl = d.x[lo], xh = d.x[hi];
+                const double bl = 1.0 / (kBoltzmannEv * d.T_site[lo]);
+                const double bh = 1.0 / (kBoltzmannEv * d.T_site[hi]);
+                const double r_hl = m.nu0 * exp(-bh * m.Qm) * exp(m.kin_c * bh * (d.mu[hi] - d.mu[lo]));
+                const double r_lh = m.nu0 * exp(-bl * m.Qm) * exp(m.kin_c * bl * (d.mu[lo] - d.mu[hi]));
+                const double J = xh * (1.0 - xl) * r_hl - xl * (1.0 - xh) * r_lh;  // net hi -> lo
+                acc += i_lo ? J : -J;
+                const double xj = i_lo ? xh : xl;
+                rout += (1.0 - xj) * (i_lo ? r_lh : r_hl);
+                rin += xj * (i_lo ? r_hl : r_lh);
+            }
+        } else if (occ_mobile(ti)) {
             const double D = S.D, cb = m.kin_c * S.beta;
             const int nb = d.nbond[i];
             const int* row = d.bond + (int64_t)i * d.bond_max;

@@ -23,10 +23,10 @@ S_F, S_FMAX, S_DT, S_TIME, S_SUMX, S_UPDATES, S_CONVERGED, S_EVALS, S_STATUS, S_
     S_TOTAL_EVALS, S_PAIRS, S_PAIR_EVALS, S_RESERVOIR = range(14)
 K_PAIR, K_DENSITY, K_FORCE, K_BUILD, K_FIRE, K_MASTER = range(6)
 KERNEL_FAMILIES = ["pair", "density", "force", "build", "fire", "master"]
-STAT_NONFINITE, STAT_X_RANGE, STAT_RHO, STAT_SIGMA_MIN, STAT_KMAX, _STAT_RESERVED, STAT_PAIRS, \
+STAT_NONFINITE, STAT_X_RANGE, STAT_RHO, STAT_SIGMA_MIN, STAT_KMAX, STAT_TEMP, STAT_PAIRS, \
     STAT_BONDS, STAT_SIGMA_CAP = (1 << k for k in range(9))
 FATAL_STATUS = STAT_NONFINITE | STAT_X_RANGE | STAT_RHO | STAT_KMAX | STAT_PAIRS | STAT_BONDS | \
-    STAT_SIGMA_CAP
+    STAT_SIGMA_CAP | STAT_TEMP
 
 EXPORTED = ["mxe_default_params", "mxe_plan_create", "mxe_plan_destroy", "mxe_workspace_bytes",
             "mxe_plan_sites", "mxe_plan_set_system", "mxe_plan_slot_offset", "mxe_plan_set_resume",
@@ -60,7 +60,7 @@ class System(C.Structure):
 class State(C.Structure):
     _fields_ = [("qx", C.c_void_p), ("qy", C.c_void_p), ("qz", C.c_void_p),
                 ("sigma", C.c_void_p), ("x", C.c_void_p), ("type", C.c_void_p),
-                ("reservoir", C.c_void_p), ("res_value", C.c_void_p)]
+                ("reservoir", C.c_void_p), ("res_value", C.c_void_p), ("T_site", C.c_void_p)]
 
 
 class Out(C.Structure):
@@ -175,12 +175,13 @@ class DeviceState:
     type: "torch.Tensor"
     reservoir: "torch.Tensor" = None   # int8 kinds (RES_*), optional
     res_value: "torch.Tensor" = None   # held x or mu, FP64, optional
+    T_site: "torch.Tensor" = None      # per-site temperature (K), FP64, optional
 
     def abi(self) -> State:
         opt = lambda t: t.data_ptr() if t is not None else None
         return State(self.qx.data_ptr(), self.qy.data_ptr(), self.qz.data_ptr(),
                      self.sigma.data_ptr(), self.x.data_ptr(), self.type.data_ptr(),
-                     opt(self.reservoir), opt(self.res_value))
+                     opt(self.reservoir), opt(self.res_value), opt(self.T_site))
 
     def q(self):
         import torch
