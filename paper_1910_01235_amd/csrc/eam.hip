@@ -42,22 +42,19 @@ namespace {
 //    sin(pi t) = cos z, from their Taylor series to degrees 21 and 20.
 // The FP32 variant uses the hardware exp2, rsq and sin/cos instructions.
 // ---------------------------------------------------------------------------
-__device__ inline double exp_bounded(double x) {
+// The polynomial coefficients arrive in the kernel arguments (Model::poly):
+// the kernels read them with scalar loads and each FMA takes its coefficient
+// as a scalar operand. An FP64 FMA cannot encode a 64-bit literal, so
+// compile-time constants would cost a move into vector registers at every use.
+__device__ inline double exp_bounded(double x, const PolyCoef& c) {
     constexpr double kLog2e = 1.4426950408889634;
     constexpr double kLn2Hi = 0.6931471803691238;      // 32 significant bits
     constexpr double kLn2Lo = 1.9082149292705877e-10;  // ln 2 - kLn2Hi
     const double n = rint(x * kLog2e);
     const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, x));
-    double p = 2.08767569878681e-09;  // 1/12!
-    p = fma(p, r, 2.505210838544172e-08);
-    p = fma(p, r, 2.755731922398589e-07);
-    p = fma(p, r, 2.7557319223985893e-06);
-    p = fma(p, r, 2.48015873015873e-05);
-    p = fma(p, r, 0.0001984126984126984);
-    p = fma(p, r, 0.001388888888888889);
-    p = fma(p, r, 0.008333333333333333);
-    p = fma(p, r, 0.041666666666666664);
-    p = fma(p, r, 0.16666666666666666);
+    double p = c.ex[0];
+#pragma unroll
+    for (int k = 1; k < PolyCoef::kExp; ++k) p = fma(p, r, c.ex[k]);
     p = fma(p, r, 0.5);
     p = fma(p, r, 1.0);
     p = fma(p, r, 1.0);
@@ -73,31 +70,18 @@ __device__ inline double rsqrt_refined(double a) {
 }
 
 // S(t) = (1 + cos(pi t)) / 2 and sin(pi t) for t in [0, 1]
-__device__ inline void taper_terms(double t, double& S, double& sn) {
+__device__ inline void taper_terms(double t, double& S, double& sn, const PolyCoef& c) {
     constexpr double kPi = 3.141592653589793;
     const double z = kPi * (t - 0.5);
     const double z2 = z * z;
-    double ps = -1.9572941063391263e-20;  // sin z: z - z^3/3! + ... - z^21/21! (odd terms)
-    ps = fma(ps, z2, 8.22063524662433e-18);
-    ps = fma(ps, z2, -2.8114572543455206e-15);
-    ps = fma(ps, z2, 7.647163731819816e-13);
-    ps = fma(ps, z2, -1.6059043836821613e-10);
-    ps = fma(ps, z2, 2.505210838544172e-08);
-    ps = fma(ps, z2, -2.7557319223985893e-06);
-    ps = fma(ps, z2, 0.0001984126984126984);
-    ps = fma(ps, z2, -0.008333333333333333);
-    ps = fma(ps, z2, 0.16666666666666666);
+    double ps = c.sn[0];  // sin z = z (1 - z^2 (1/3! - z^2 (1/5! - ...)))
+#pragma unroll
+    for (int k = 1; k < PolyCoef::kSin; ++k) ps = fma(ps, z2, c.sn[k]);
     ps = fma(-ps, z2, 1.0);
     const double sinz = ps * z;
-    double pc = 4.110317623312165e-19;  // cos z: 1 - z^2/2! + ... + z^20/20!
-    pc = fma(pc, z2, -1.5619206968586225e-16);
-    pc = fma(pc, z2, 4.779477332387385e-14);
-    pc = fma(pc, z2, -1.1470745597729725e-11);
-    pc = fma(pc, z2, 2.08767569878681e-09);
-    pc = fma(pc, z2, -2.755731922398589e-07);
-    pc = fma(pc, z2, 2.48015873015873e-05);
-    pc = fma(pc, z2, -0.001388888888888889);
-    pc = fma(pc, z2, 0.041666666666666664);
+    double pc = c.cs[0];
+#pragma unroll
+    for (int k = 1; k < PolyCoef::kCos; ++k) pc = fma(pc, z2, c.cs[k]);
     pc = fma(pc, z2, -0.5);
     pc = fma(pc, z2, 1.0);
     S = 0.5 * (1.0 - sinz);
@@ -107,14 +91,16 @@ __device__ inline void taper_terms(double t, double& S, double& sn) {
 template <typename T> struct Math;
 
 template <> struct Math<double> {
-    static __device__ inline double ex(double v) { return exp_bounded(v); }
+    static __device__ inline double ex(double v, const PolyCoef& c) { return exp_bounded(v, c); }
     static __device__ inline double rsq(double v) { return rsqrt_refined(v); }
-    static __device__ inline void taper(double t, double& S, double& sn) { taper_terms(t, S, sn); }
+    static __device__ inline void taper(double t, double& S, double& sn, const PolyCoef& c) {
+        taper_terms(t, S, sn, c);
+    }
 };
 template <> struct Math<float> {
-    static __device__ inline float ex(float v) { return __expf(v); }
+    static __device__ inline float ex(float v, const PolyCoef&) { return __expf(v); }
     static __device__ inline float rsq(float v) { return __frsqrt_rn(v); }
-    static __device__ inline void taper(float t, float& S, float& sn) {
+    static __device__ inline void taper(float t, float& S, float& sn, const PolyCoef&) {
         float c;
         sincospif(t, &sn, &c);
         S = 0.5f * (1.0f + c);
@@ -124,14 +110,15 @@ template <> struct Math<float> {
 // Radial shapes of both pair functions at distance r (r < r_c):
 // g = exp(-a (r/r_e - 1)) S(r), and their derivatives.
 template <typename T>
-__device__ inline void shapes(T r, T inv_re, T al, T ga, T r_s, T tw, T& gp, T& dgp, T& gf, T& dgf) {
+__device__ inline void shapes(T r, T inv_re, T al, T ga, T r_s, T tw, T& gp, T& dgp, T& gf, T& dgf,
+                              const PolyCoef& pc) {
     const T u = r * inv_re - T(1);
-    const T ep = Math<T>::ex(-al * u);
-    const T ef = Math<T>::ex(-ga * u);
+    const T ep = Math<T>::ex(-al * u, pc);
+    const T ef = Math<T>::ex(-ga * u, pc);
     T S = T(1), dS = T(0);
     if (r > r_s) {
         T sn;
-        Math<T>::taper((r - r_s) * tw, S, sn);
+        Math<T>::taper((r - r_s) * tw, S, sn, pc);
         dS = T(-0.5) * T(3.14159265358979323846) * tw * sn;
     }
     gp = ep * S;
@@ -170,7 +157,7 @@ __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, dou
                     const T rinv = Math<T>::rsq(r2);
                     const T r = r2 * rinv;
                     T gp, dgp, gf, dgf;
-                    shapes<T>(r, inv_re, al, ga, r_s, tw, gp, dgp, gf, dgf);
+                    shapes<T>(r, inv_re, al, ga, r_s, tw, gp, dgp, gf, dgf, m.poly);
                     // node offset zeta = sqrt(3) (a-1, b-1, c-1); d . zeta
                     T dz = T(0);
                     if (a != 1) dz += (a == 2 ? X[a] : -X[a]);
@@ -209,12 +196,12 @@ __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, dou
 
 // One radial shape and its derivative at r < r_c.
 template <typename T>
-__device__ inline void one_shape(T r, T inv_re, T a, T r_s, T tw, T& g, T& dg) {
-    const T e = Math<T>::ex(-a * (r * inv_re - T(1)));
+__device__ inline void one_shape(T r, T inv_re, T a, T r_s, T tw, T& g, T& dg, const PolyCoef& pc) {
+    const T e = Math<T>::ex(-a * (r * inv_re - T(1)), pc);
     T S = T(1), dS = T(0);
     if (r > r_s) {
         T sn;
-        Math<T>::taper((r - r_s) * tw, S, sn);
+        Math<T>::taper((r - r_s) * tw, S, sn, pc);
         dS = T(-0.5) * T(3.14159265358979323846) * tw * sn;
     }
     g = e * S;
@@ -251,7 +238,7 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
                     const T rinv = Math<T>::rsq(r2);
                     const T r = r2 * rinv;
                     T gp, dgp, gf, dgf;
-                    shapes<T>(r, inv_re, al, ga, r_s, tw, gp, dgp, gf, dgf);
+                    shapes<T>(r, inv_re, al, ga, r_s, tw, gp, dgp, gf, dgf, m.poly);
                     const T cp = W * dgp * rinv, cf = W * dgf * rinv;
                     out[M_PHI] += W * gp;
                     out[M_F] += W * gf;
@@ -277,7 +264,7 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
     if (r2c < rc2 && r2c > T(0)) {  // the density at the mean positions
         const T rinv = Math<T>::rsq(r2c);
         T gf, dgf;
-        one_shape<T>(r2c * rinv, inv_re, ga, r_s, tw, gf, dgf);
+        one_shape<T>(r2c * rinv, inv_re, ga, r_s, tw, gf, dgf, m.poly);
         const T g0 = dgf * rinv;
         out[M_F0] = gf;
         out[M_GF0 + 0] = g0 * R[0];

@@ -64,6 +64,17 @@ struct Chunk {
     int pad;
 };
 
+// Polynomial coefficients of the FP64 node arithmetic (Taylor series of e^r
+// to degree 12, of sin z to degree 21 and cos z to degree 20, highest
+// degree first). They travel in the kernel arguments so that the kernels read
+// them into scalar registers.
+struct PolyCoef {
+    static constexpr int kExp = 10, kSin = 10, kCos = 9;
+    double ex[kExp];  // 1/12!, ..., 1/3! (the terms 1/2!, 1, 1 are inline constants)
+    double sn[kSin];  // -1/21!, 1/19!, ..., -1/5!, 1/3!  (sin z = z (1 - z^2 (1/3! - ...)))
+    double cs[kCos];  // 1/20!, -1/18!, ..., 1/4! (the terms -1/2!, 1 are inline constants)
+};
+
 // Analytic EAM and run parameters, passed by value to the kernels.
 struct Model {
     double c4[4], b4[4];    // per species (A, B, S, none): embedding strength, emission
@@ -75,6 +86,7 @@ struct Model {
     double sigma_min, sigma_cap, skin, r_bond, kin_c, dt_safety, nu0, Qm;
     int gather_lanes, pair_block;  // launch shapes (tuned per workload)
     int quad_rule;                 // MXE_QUAD_GH27 or MXE_QUAD_DEGREE3
+    PolyCoef poly;
 };
 
 // Every device pointer the kernels use.
