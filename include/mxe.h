@@ -103,7 +103,7 @@ typedef struct {
     double sigma_cap;    /* widths above this flag MXE_STAT_SIGMA_CAP; sizes the cells */
     double skin;         /* neighbour-list skin (A)                           */
     double r_bond;       /* kinetic-law bond radius: same-type sites closer   */
-    int k_max;           /* neighbour-list row length (max neighbours/site)   */
+    int k_max;           /* neighbour-list row length (max neighbours/site), <= 256 */
     int bond_max;        /* max bonds per site                                */
     mxe_precision precision;
     /* launch shapes (performance only; results do not depend on them beyond

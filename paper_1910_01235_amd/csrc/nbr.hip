@@ -249,25 +249,73 @@ __device__ inline int64_t stencil_lane_cell(const SysDesc& S, const int c[3], in
     return S.cell_off + ((int64_t)v[0] * S.nc[1] + v[1]) * S.nc[2] + v[2];
 }
 
+// Bitonic sort of 64 E ints held E per lane (element r * 64 + lane), ascending.
+// Partners closer than 64 sit in other lanes (exchanged by shuffles), partners
+// 64 or more apart in the same lane.
+template <int E>
+__device__ inline void wave_sort(int (&v)[E], int lane) {
+    constexpr int N = kWave * E;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= kWave) {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const int r2 = r ^ (j / kWave);
+                    if (r2 > r) {
+                        const bool asc = ((r * kWave + lane) & k) == 0;
+                        const int a = v[r], b = v[r2];
+                        const bool swap = (a > b) == asc;
+                        v[r] = swap ? b : a;
+                        v[r2] = swap ? a : b;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const int o = __shfl_xor(v[r], j);
+                    const bool lower = (lane & j) == 0;
+                    const bool asc = ((r * kWave + lane) & k) == 0;
+                    v[r] = (lower == asc) ? min(v[r], o) : max(v[r], o);
+                }
+            }
+        }
+    }
+}
+
+constexpr int kCandTile = 1024;  // candidate positions staged per wave and pass
+
 // One wavefront per site. Lanes 0-26 each take one stencil cell; a wave scan
-// of the cell counts turns the stencil into one flat candidate list that the
-// lanes walk in strides of 64. Candidates within the pair's list radius are
-// compacted by ballot into an LDS row, which is then sorted (bitonic).
-__global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int K2) {
-    extern __shared__ int lds_rows[];  // kChunk / kWave rows of K2 entries
-    __shared__ int cstart[kChunk / kWave][32], cpre[kChunk / kWave][33];
-    __shared__ int wave_up[kChunk / kWave];
+// of the cell counts lays the stencil out as one flat candidate list, whose
+// record positions the stencil lanes write into an LDS table (in tiles of
+// kCandTile). All lanes then walk the table in strides of 64, testing each
+// candidate against the pair's list radius; hits are compacted by ballot into
+// an LDS row, which is sorted in registers (E entries per lane).
+// The radius test is a superset test: the minimum image uses the reciprocal
+// box length and s_ij an FP32 square root, and the radius is padded by 1e-6 A,
+// so every pair the exact test admits is admitted (an extra pair whose nodes
+// all lie beyond r_c contributes exact zeros).
+template <int E>
+__global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
+    constexpr int K2 = kWave * E;
+    constexpr int kWaves = kChunk / kWave;
+    __shared__ int rows[kWaves][K2];
+    __shared__ int cand[kWaves][kCandTile];
+    __shared__ int wave_up[kWaves];
     const Chunk ch = d.chunks[blockIdx.x];
     const int s = ch.sys;
     if (!d.ctl[s].rebuild) return;
     const SysDesc& S = d.sys[s];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int* row = lds_rows + wave * K2;
+    int* row = rows[wave];
+    int* ctab = cand[wave];
     const int K = d.K;
-    const double reach = m.r_c + m.skin;
+    const double reach = m.r_c + m.skin + 1e-6;
+    const double ib0 = 1.0 / S.box[0], ib1 = 1.0 / S.box[1], ib2 = 1.0 / S.box[2];
     int up_sum = 0;
     bool over = false;
-    for (int i = ch.start + wave; i < ch.end; i += kChunk / kWave) {
+    for (int i = ch.start + wave; i < ch.end; i += kWaves) {
         const double qi0 = d.qx[i], qi1 = d.qy[i], qi2 = d.qz[i];
         const double si2 = d.sigma[i] * d.sigma[i];
         const int ti = d.type[i];
@@ -289,83 +337,74 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int K2) {
             const int u = __shfl_up(incl, o);
             if (lane >= o) incl += u;
         }
-        if (lane < 32) {
-            cstart[wave][lane] = start_c;
-            cpre[wave][lane + 1] = incl;
-        }
-        if (lane == 0) cpre[wave][0] = 0;
+        const int pre = incl - cnt_c;
         const int total = __shfl(incl, 31);
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         int n = 0;
-        // each lane takes kCand candidates per pass (independent load chains)
-        constexpr int kCand = 4;
-        for (int base = 0; base < total; base += kWave * kCand) {
-            int jc[kCand];
-            bool okc[kCand];
+        for (int t0 = 0; t0 < total; t0 += kCandTile) {
+            const int t1 = min(total, t0 + kCandTile);
+            // stencil lanes write the record positions of their cell's part of the tile
+            if (cnt_c > 0) {
+                const int a = max(pre, t0), b = min(pre + cnt_c, t1);
+                for (int e = a; e < b; ++e) ctab[e - t0] = start_c + (e - pre);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            constexpr int kCand = 4;  // candidates per lane and pass (independent loads)
+            for (int base = t0; base < t1; base += kWave * kCand) {
+                int jc[kCand];
+                bool okc[kCand];
 #pragma unroll
-            for (int u = 0; u < kCand; ++u) {
-                const int e = base + u * kWave + lane;
-                jc[u] = -1;
-                bool ok = false;
-                if (e < total) {
-                    // cell holding flat index e: the last with cpre <= e (cells may be empty)
-                    int lo = 0, hi = 31;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (cpre[wave][mid] <= e) lo = mid; else hi = mid - 1;
+                for (int u = 0; u < kCand; ++u) {
+                    const int e = base + u * kWave + lane;
+                    jc[u] = -1;
+                    bool ok = false;
+                    if (e < t1) {
+                        const int pos = ctab[e - t0];
+                        const int jt = d.cell_sites[pos];
+                        const int j = jt >> 2;
+                        jc[u] = j;
+                        if (j != i && pair_cls(ti, jt & 3) >= 0) {
+                            const double4 rj = d.cell_rec[pos];
+                            double dx = rj.x - qi0, dy = rj.y - qi1, dz = rj.z - qi2;
+                            if (S.periodic[0]) dx -= S.box[0] * rint(dx * ib0);
+                            if (S.periodic[1]) dy -= S.box[1] * rint(dy * ib1);
+                            if (S.periodic[2]) dz -= S.box[2] * rint(dz * ib2);
+                            const float sf = __builtin_sqrtf((float)(si2 + rj.w * rj.w));
+                            const double rl = reach + 3.0 * (double)sf;
+                            ok = dx * dx + dy * dy + dz * dz < rl * rl;
+                        }
                     }
-                    const int pos = cstart[wave][lo] + (e - cpre[wave][lo]);
-                    const int jt = d.cell_sites[pos];
-                    const int j = jt >> 2;
-                    jc[u] = j;
-                    if (j != i && pair_cls(ti, jt & 3) >= 0) {
-                        const double4 rj = d.cell_rec[pos];
-                        double dx = rj.x - qi0, dy = rj.y - qi1, dz = rj.z - qi2;
-                        min_image(S, dx, dy, dz);
-                        const double rl = reach + 3.0 * sqrt(si2 + rj.w * rj.w);
-                        ok = dx * dx + dy * dy + dz * dz < rl * rl;
-                    }
+                    okc[u] = ok;
                 }
-                okc[u] = ok;
-            }
 #pragma unroll
-            for (int u = 0; u < kCand; ++u) {
-                const unsigned long long mask = __ballot(okc[u]);
-                const int pos = n + __popcll(mask & __lanemask_lt());
-                if (okc[u] && pos < K2) row[pos] = jc[u];
-                n += __popcll(mask);
+                for (int u = 0; u < kCand; ++u) {
+                    const unsigned long long mask = __ballot(okc[u]);
+                    const int pos = n + __popcll(mask & __lanemask_lt());
+                    if (okc[u] && pos < K2) row[pos] = jc[u];
+                    n += __popcll(mask);
+                }
             }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
         if (n > K) over = true;
         const int nk = min(n, K);
-        for (int k = nk + lane; k < K2; k += kWave) row[k] = 0x7fffffff;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        // bitonic sort of the K2-entry row (ascending)
-        for (int kk = 2; kk <= K2; kk <<= 1) {
-            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int t = lane; t < K2; t += kWave) {
-                    const int u = t ^ jj;
-                    if (u > t) {
-                        const int a = row[t], b = row[u];
-                        const bool asc = (t & kk) == 0;
-                        if ((a > b) == asc) {
-                            row[t] = b;
-                            row[u] = a;
-                        }
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            }
+        int v[E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int t = r * kWave + lane;
+            v[r] = t < min(n, K2) ? row[t] : 0x7fffffff;
         }
+        wave_sort<E>(v, lane);
         int lo = 0;
         int* out = d.nbr + (int64_t)i * K;
-        for (int k = lane; k < nk; k += kWave) {
-            const int j = row[k];
-            out[k] = j;
-            lo += (j < i);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int t = r * kWave + lane;
+            if (t < nk) {
+                out[t] = v[r];
+                lo += (v[r] < i);
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) lo += __shfl_xor(lo, o);
@@ -384,7 +423,7 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int K2) {
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
-        for (int w = 0; w < kChunk / kWave; ++w) t += wave_up[w];
+        for (int w = 0; w < kWaves; ++w) t += wave_up[w];
         d.chunk_up[blockIdx.x] = t;
     }
 }
@@ -549,8 +588,11 @@ void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s) {
     k_bin<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_fill<<<d.n_chunks, kChunk, 0, s>>>(d);
-    const int K2 = row_pow2(d.K);
-    k_nbr<<<d.n_chunks, kChunk, (size_t)(kChunk / kWave) * K2 * sizeof(int), s>>>(d, m, K2);
+    switch (row_pow2(d.K)) {
+        case 64: k_nbr<1><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        case 128: k_nbr<2><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        default: k_nbr<4><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+    }
     if (bonds) k_bonds<<<d.n_chunks, kChunk, 0, s>>>(d, m);
     k_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_half<<<d.n_chunks, kChunk, 0, s>>>(d);
