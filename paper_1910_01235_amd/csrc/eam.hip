@@ -290,6 +290,8 @@ struct alignas(16) Vec16 {
 
 template <typename T, int kBS, int kRule>
 __global__ __launch_bounds__(kBS, 3) void k_pair(Dev d, Model m) {
+    // pair chunks are sized to capacity and only the leading ones are active,
+    // so they keep the plain order (contiguous ranges per XCD would idle XCDs)
     const Chunk ch = d.pchunks[blockIdx.x];
     const SysCtl& c = d.ctl[ch.sys];
     if (c.done) return;
@@ -341,7 +343,9 @@ __device__ inline double group_sum(double v) {
 template <typename T, int kLPS>
 __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
     constexpr int kGroups = kChunk / kLPS;
-    const Chunk ch = d.chunks[blockIdx.x];
+    const int cb = xcd_chunk(d.n_chunks);
+    if (cb >= d.n_chunks) return;
+    const Chunk ch = d.chunks[cb];
     if (d.ctl[ch.sys].done) return;
     const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
     const T* dblk = (const T*)d.dblk;
@@ -424,7 +428,9 @@ template <typename T, int kLPS>
 __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
     constexpr int kGroups = kChunk / kLPS;
     __shared__ double red[kGroups][6];
-    const Chunk ch = d.chunks[blockIdx.x];
+    const int cb = xcd_chunk(d.n_chunks);
+    if (cb >= d.n_chunks) return;
+    const Chunk ch = d.chunks[cb];
     const int sys = ch.sys;
     if (d.ctl[sys].done) return;
     const SysDesc& S = d.sys[sys];
@@ -550,7 +556,7 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double* P = d.part + (int64_t)blockIdx.x * kNPart;
+        double* P = d.part + (int64_t)cb * kNPart;
         double e = red[0][0], fm = red[0][1], fv = red[0][2], ff = red[0][3], vv = red[0][4], sx = red[0][5];
         for (int g = 1; g < kGroups; ++g) {
             e += red[g][0];
@@ -587,20 +593,20 @@ void launch_pair_t(const Dev& d, const Model& m, int bs, hipStream_t s) {
 template <typename T>
 void launch_density_t(const Dev& d, const Model& m, int lps, hipStream_t s) {
     switch (lps) {
-        case 8: k_density<T, 8><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
-        case 32: k_density<T, 32><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
-        case 64: k_density<T, 64><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
-        default: k_density<T, 16><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        case 8: k_density<T, 8><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        case 32: k_density<T, 32><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        case 64: k_density<T, 64><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        default: k_density<T, 16><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
     }
 }
 
 template <typename T>
 void launch_force_t(const Dev& d, const Model& m, int lps, hipStream_t s) {
     switch (lps) {
-        case 8: k_force<T, 8><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
-        case 32: k_force<T, 32><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
-        case 64: k_force<T, 64><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
-        default: k_force<T, 16><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        case 8: k_force<T, 8><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        case 32: k_force<T, 32><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        case 64: k_force<T, 64><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        default: k_force<T, 16><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
     }
 }
 

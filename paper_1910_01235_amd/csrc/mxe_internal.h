@@ -169,6 +169,19 @@ __device__ inline double mixdx(const double* v4, int t) {
 
 // index ranges for grid-stride loops
 __device__ inline int gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
+
+// XCD-aware chunk order. The hardware deals workgroups to the 8 XCDs in turn,
+// so consecutive chunks (neighbouring sites) would land in 8 different L2
+// caches. Workgroup b takes chunk (b % 8) * per + b / 8 instead: each XCD
+// sweeps one contiguous range of chunks and the neighbours' data a gather
+// reads (pair blocks from both ends, site records) stay in its own L2.
+// Launch xcd_grid(n) workgroups; a workgroup whose chunk is >= n exits.
+constexpr int kXcd = 8;
+__device__ inline int xcd_chunk(int n) {
+    const int per = (n + kXcd - 1) / kXcd;
+    return (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
+}
+inline int xcd_grid(int n) { return (n + kXcd - 1) / kXcd * kXcd; }
 __device__ inline int gstride() { return gridDim.x * blockDim.x; }
 
 // binary search for the system that owns global index `idx` given an

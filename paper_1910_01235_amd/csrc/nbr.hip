@@ -303,7 +303,9 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
     __shared__ int rows[kWaves][K2];
     __shared__ int cand[kWaves][kCandTile];
     __shared__ int wave_up[kWaves];
-    const Chunk ch = d.chunks[blockIdx.x];
+    const int cb = xcd_chunk(d.n_chunks);
+    if (cb >= d.n_chunks) return;
+    const Chunk ch = d.chunks[cb];
     const int s = ch.sys;
     if (!d.ctl[s].rebuild) return;
     const SysDesc& S = d.sys[s];
@@ -424,7 +426,7 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
     if (threadIdx.x == 0) {
         int t = 0;
         for (int w = 0; w < kWaves; ++w) t += wave_up[w];
-        d.chunk_up[blockIdx.x] = t;
+        d.chunk_up[cb] = t;
     }
 }
 
@@ -525,7 +527,9 @@ __global__ __launch_bounds__(kChunk) void k_half(Dev d) {
 // is owned by the lower site; for j < i it is found by binary search of i in
 // j's sorted row (i lies in j's upper part).
 __global__ __launch_bounds__(kChunk) void k_pid(Dev d) {
-    const Chunk ch = d.chunks[blockIdx.x];
+    const int cb = xcd_chunk(d.n_chunks);
+    if (cb >= d.n_chunks) return;
+    const Chunk ch = d.chunks[cb];
     const int s = ch.sys;
     if (!d.ctl[s].rebuild) return;
     const SysDesc& S = d.sys[s];
@@ -589,14 +593,14 @@ void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s) {
     k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_fill<<<d.n_chunks, kChunk, 0, s>>>(d);
     switch (row_pow2(d.K)) {
-        case 64: k_nbr<1><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
-        case 128: k_nbr<2><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
-        default: k_nbr<4><<<d.n_chunks, kChunk, 0, s>>>(d, m); break;
+        case 64: k_nbr<1><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        case 128: k_nbr<2><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        default: k_nbr<4><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
     }
     if (bonds) k_bonds<<<d.n_chunks, kChunk, 0, s>>>(d, m);
     k_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_half<<<d.n_chunks, kChunk, 0, s>>>(d);
-    k_pid<<<d.n_chunks, kChunk, 0, s>>>(d);
+    k_pid<<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d);
     k_build_done<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d);
 }
 
