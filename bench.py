@@ -45,12 +45,12 @@ BYTES_FORCE_PER_SITE = 8 + 8 + 1 + 8 * 3 + 8 * 4 + 8 * 6
 # KiB per dispatch averaged over the run's dispatches, scaled by what the same
 # counters read for a 1 GiB device copy (FETCH x 2, WRITE x 1). Valid only for
 # the kernel sources they were taken on: a different source hash reports null.
-COUNTER_SCALE = dict(fetch=2.0, write=1.0)
+COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="07bbd395bfc21132",
-    pair=dict(fetch_kib=80009.2, write_kib=1018955.3),
-    force=dict(fetch_kib=1166584.4, write_kib=13535.3),
-    density=dict(fetch_kib=317785.7, write_kib=27785.8),
+    sources_sha256_16="e48300592688565e",
+    pair=dict(fetch_kib=87315.3, write_kib=1019434.9),
+    force=dict(fetch_kib=1093538.3, write_kib=13606.8),
+    density=dict(fetch_kib=277326.3, write_kib=27765.5),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
