@@ -48,7 +48,7 @@ struct mxe_plan {
     // workspace layout (byte offsets)
     size_t o_sys, o_ctl, o_chunks, o_pchunks, o_site_sys, o_cell_count, o_cell_start, o_cell_sites, o_cell_rec;
     size_t o_cell_of, o_slot_of, o_chunk_up, o_chunk_off;
-    size_t o_nbr, o_cnt, o_lo, o_pid, o_hoff, o_pi, o_pj, o_fblk, o_dblk, o_G, o_A, o_B;
+    size_t o_nbr, o_cnt, o_lo, o_pid, o_hoff, o_pi, o_pj, o_pnew, o_fblk, o_dblk, o_G, o_A, o_B;
     size_t o_v, o_qr, o_sref, o_emit, o_srec, o_bond, o_nbond, o_part;
     size_t ws_bytes = 0;
     // graph cache for mxe_run
@@ -332,6 +332,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     P->o_pid = take(sizeof(int) * N * p.k_max);
     P->o_hoff = take(sizeof(int) * N);
     P->o_pi = take(sizeof(int) * P->pair_cap_total);
+    P->o_pnew = take(sizeof(int) * P->pair_cap_total);
     P->o_pj = take(sizeof(int) * P->pair_cap_total);
     P->o_fblk = take(mom_elt * kFBlk * P->pair_cap_total);
     P->o_dblk = take(mom_elt * 2 * P->pair_cap_total);
@@ -425,6 +426,7 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.pid = (int*)(w + P->o_pid);
     D.half_off = (int*)(w + P->o_hoff);
     D.pair_i = (int*)(w + P->o_pi);
+    D.pnew = (int*)(w + P->o_pnew);
     D.pair_j = (int*)(w + P->o_pj);
     D.fblk = (void*)(w + P->o_fblk);
     D.dblk = (void*)(w + P->o_dblk);

@@ -113,6 +113,7 @@ struct Dev {
     int *chunk_up, *chunk_off;
     int *nbr, *nbr_cnt, *nbr_lo, *pid, *half_off;
     int *pair_i, *pair_j;
+    int* pnew;         // per pair: its number after the renumbering by geometric class
     void* fblk;   // [pair][kFBlk] force blocks (T)
     void* dblk;   // [pair][2] density pair (<f>, f0) (T)
     double *G, *Ahat, *Bhat;

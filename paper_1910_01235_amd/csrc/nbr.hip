@@ -571,6 +571,90 @@ __global__ __launch_bounds__(kChunk) void k_pid(Dev d) {
     if (bad) atomicOr(&d.ctl[s].status, MXE_STAT_KMAX);
 }
 
+// Pair numbering by geometric class. Within each pair chunk the pairs are
+// renumbered so that pairs of one class are consecutive: the distance |rbar|
+// in 0.25-A bins, the octant of rbar and its dominant axis. A wavefront of the
+// pair kernel then holds pairs of similar geometry, whose quadrature nodes
+// take the same branches (inside or beyond r_c, inside or within the taper),
+// so whole wavefronts skip nodes beyond r_c and the taper polynomial where no
+// pair needs them. The pair endpoints are permuted in place (each block reads
+// its whole chunk before writing it) and the new number of each old pair goes
+// to pnew, from which k_pid_remap rewrites the rows' pair ids. Numbers within
+// a bucket come from LDS atomics: the assignment of numbers may vary from run
+// to run, but each pair's moments do not depend on its number, and every
+// gather sums over its row in row order, so results are unchanged.
+constexpr int kPairBins = 32 * 24;
+
+__global__ __launch_bounds__(kChunk) void k_pair_order(Dev d) {
+    __shared__ int cnt[kPairBins], start[kPairBins];
+    const Chunk ch = d.pchunks[blockIdx.x];
+    const SysCtl& c = d.ctl[ch.sys];
+    if (!c.rebuild) return;
+    const SysDesc& S = d.sys[ch.sys];
+    const int64_t pend = min((int64_t)ch.end, S.pair_base + min((int64_t)c.n_pairs, S.pair_cap));
+    if (pend <= ch.start) return;
+    for (int b = threadIdx.x; b < kPairBins; b += blockDim.x) cnt[b] = 0;
+    __syncthreads();
+    constexpr int kPer = kPairChunk / kChunk;
+    int key[kPer], pi[kPer], pj[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int64_t p = ch.start + (int64_t)u * kChunk + threadIdx.x;
+        key[u] = -1;
+        pi[u] = pj[u] = 0;
+        if (p < pend) {
+            const int i = d.pair_i[p], j = d.pair_j[p];
+            pi[u] = i;
+            pj[u] = j;
+            double rx = d.qx[j] - d.qx[i], ry = d.qy[j] - d.qy[i], rz = d.qz[j] - d.qz[i];
+            min_image(S, rx, ry, rz);
+            const double ax = fabs(rx), ay = fabs(ry), az = fabs(rz);
+            const double db = sqrt(rx * rx + ry * ry + rz * rz) * 4.0;
+            const int rb = (db >= 0.0 && db < 31.0) ? (int)db : 31;  // a NaN position lands in bin 31
+            const int oct = (rx < 0.0 ? 4 : 0) + (ry < 0.0 ? 2 : 0) + (rz < 0.0 ? 1 : 0);
+            const int dom = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+            key[u] = rb * 24 + oct * 3 + dom;
+            atomicAdd(&cnt[key[u]], 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int b = 0; b < kPairBins; ++b) {
+            start[b] = run;
+            run += cnt[b];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        if (key[u] < 0) continue;
+        const int64_t p = ch.start + (int64_t)u * kChunk + threadIdx.x;
+        const int64_t t = ch.start + atomicAdd(&start[key[u]], 1);
+        d.pair_i[t] = pi[u];
+        d.pair_j[t] = pj[u];
+        d.pnew[p] = (int)t;
+    }
+}
+
+// Rows' pair ids follow the renumbering of k_pair_order.
+__global__ __launch_bounds__(kChunk) void k_pid_remap(Dev d) {
+    const int cb = xcd_chunk(d.n_chunks);
+    if (cb >= d.n_chunks) return;
+    const Chunk ch = d.chunks[cb];
+    if (!d.ctl[ch.sys].rebuild) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int K = d.K;
+    for (int i = ch.start + wave; i < ch.end; i += kChunk / kWave) {
+        const int cnt = d.nbr_cnt[i];
+        int* prow = d.pid + (int64_t)i * K;
+        for (int k = lane; k < cnt; k += kWave) {
+            const int p = prow[k];
+            if (p >= 0) prow[k] = d.pnew[p];
+        }
+    }
+}
+
 __global__ void k_build_done(Dev d) {
     const int s = gtid();
     if (s >= d.n_sys) return;
@@ -601,6 +685,8 @@ void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s) {
     k_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_half<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_pid<<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d);
+    k_pair_order<<<d.n_pchunks, kChunk, 0, s>>>(d);
+    k_pid_remap<<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d);
     k_build_done<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d);
 }
 
