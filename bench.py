@@ -298,6 +298,32 @@ def main():
             log(f"degree-3 {prec} leg: {wall3:.3f} s")
             del st3, out3, ws3, p3
             torch.cuda.empty_cache()
+        # state variants on the same workload: site temperatures, reservoir sites
+        result["variants"] = {}
+        rng = np.random.default_rng(3)
+        for name in ("site_temperature", "reservoirs"):
+            pv = mxe.Plan([s], w.eam, w.params, precision="fp64")
+            stv, outv, wsv = pv.state([s]), pv.out(), pv.workspace()
+            if name == "site_temperature":
+                stv.T_site = torch.as_tensor(900.0 + 200.0 * s.q[:, 0] / s.box[0], device="cuda")
+            else:
+                held = rng.choice(n, n // 100, replace=False)
+                res = np.zeros(n, np.int8)
+                res[held[: len(held) // 2]] = mxe.RES_FIX_X
+                res[held[len(held) // 2:]] = mxe.RES_FIX_MU
+                val = np.where(res == mxe.RES_FIX_X, 1.0, -0.85)
+                stv.reservoir = torch.as_tensor(res, device="cuda")
+                stv.res_value = torch.as_tensor(val, device="cuda")
+            pv.run(stv, outv, wsv, args.warmup, use_graph=True)
+            wall_v, sc_v, prof_v = timed_run(pv, stv, outv, wsv, args.steps, use_graph=False, profile=True)
+            evv = int(sc_v[mxe.S_TOTAL_EVALS])
+            result["variants"][name] = dict(
+                value=n * evv / wall_v, ms_per_step=wall_v / args.steps * 1e3, evals=evv,
+                status=int(sc_v[mxe.S_STATUS]),
+                kernel_ms_avg={k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof_v.items()})
+            log(f"{name} leg: {wall_v:.3f} s")
+            del stv, outv, wsv, pv
+            torch.cuda.empty_cache()
         t0 = time.perf_counter()
         result["many_systems"] = batched_legs(args.batch_requests, args.batch_steps)
         log(f"batched/served legs: {time.perf_counter() - t0:.1f} s")

@@ -21,11 +21,12 @@ PAIR_BLOCKS = (64, 128, 256)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mxe_autotune.json")
 
 
-def bucket(systems, precision: str) -> str:
-    """Size bucket (power of two of the total sites), precision and lattice kind."""
+def bucket(systems, precision: str, quad_rule: int = 0) -> str:
+    """Size bucket (power of two of the total sites), precision, quadrature rule and lattice kind."""
     n = sum(int(s.n) for s in systems)
     kind = "interstitial" if any((s.type == L.INTERSTITIAL).any() for s in systems) else "host"
-    return f"{precision}/{kind}/2^{int(round(math.log2(max(n, 1))))}"
+    rule = "deg3" if quad_rule == mxe.QUAD_DEGREE3 else "gh27"
+    return f"{precision}/{rule}/{kind}/2^{int(round(math.log2(max(n, 1))))}"
 
 
 class Cache:
@@ -86,7 +87,7 @@ def tune(systems, eam: dict, params: dict, precision: str = "fp64", reps: int = 
 def tuned_params(systems, eam: dict, params: dict, precision: str = "fp64", cache: Cache = None,
                  retune: bool = False, reps: int = 5):
     """params with the tuned launch shapes (tuned now, or taken from the cache)."""
-    key = bucket(systems, precision)
+    key = bucket(systems, precision, int(eam.get("quad_rule", 0)))
     hit = None if (cache is None or retune) else cache.get(key)
     if hit is None:
         hit = tune(systems, eam, params, precision, reps)

@@ -317,9 +317,12 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
     const double ib0 = 1.0 / S.box[0], ib1 = 1.0 / S.box[1], ib2 = 1.0 / S.box[2];
     int up_sum = 0;
     bool over = false;
+    const double smax = __longlong_as_double((long long)d.ctl[s].sigmax_bits);
     for (int i = ch.start + wave; i < ch.end; i += kWaves) {
         const double qi0 = d.qx[i], qi1 = d.qy[i], qi2 = d.qz[i];
         const double si2 = d.sigma[i] * d.sigma[i];
+        const double rmax = reach + 3.0 * sqrt(si2 + smax * smax) + 1e-6;
+        const double rmax2 = rmax * rmax;
         const int ti = d.type[i];
         const int c[3] = {cell_coord(qi0, S.box[0], S.cell_w[0], S.nc[0], S.periodic[0]),
                           cell_coord(qi1, S.box[1], S.cell_w[1], S.nc[1], S.periodic[1]),
@@ -327,7 +330,21 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
         int cnt_c = 0, start_c = 0;
         if (lane < 27) {
             const int64_t cell = stencil_lane_cell(S, c, lane);
-            if (cell >= 0) {
+            // skip a stencil cell whose nearest face lies beyond every radius a
+            // pair of site i can have (for periodic axes with fewer than three
+            // cells the stencil repeats cells, and that axis is not culled)
+            const int o[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
+            const double u[3] = {qi0, qi1, qi2};
+            double gap2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (o[a] == 0 || (S.periodic[a] && S.nc[a] < 3)) continue;
+                double v = u[a];
+                if (S.periodic[a]) v -= S.box[a] * floor(v / S.box[a]);
+                const double g = o[a] > 0 ? (c[a] + 1) * S.cell_w[a] - v : v - c[a] * S.cell_w[a];
+                if (g > 0.0) gap2 += g * g;
+            }
+            if (cell >= 0 && gap2 < rmax2) {
                 cnt_c = d.cell_count[cell];
                 start_c = d.cell_start[cell];
             }

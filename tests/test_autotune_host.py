@@ -8,9 +8,10 @@ from paper_1910_01235_amd import mxe
 
 def test_bucket_names():
     a = [L.vacancy_bulk(4, 0, 800.0, 0)]
-    assert autotune.bucket(a, "fp64") == "fp64/host/2^8"
+    assert autotune.bucket(a, "fp64") == "fp64/gh27/host/2^8"
+    assert autotune.bucket(a, "fp64", quad_rule=1) == "fp64/deg3/host/2^8"
     w = L.nanowire(radius=6.0, n_axial=4)
-    assert autotune.bucket([w], "fp32").startswith("fp32/interstitial/")
+    assert autotune.bucket([w], "fp32").startswith("fp32/gh27/interstitial/")
 
 
 def test_cache_round_trip(tmp_path):

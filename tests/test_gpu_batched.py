@@ -147,4 +147,4 @@ def test_autotuned_shapes_keep_results(mx, tmp_path):
     params, hit = autotune.tuned_params([s], L.DEFAULT_EAM, p, "fp64", cache=cache, reps=2)
     assert params["gather_lanes"] in autotune.GATHER_LANES
     assert params["pair_block"] in autotune.PAIR_BLOCKS
-    assert cache.get(autotune.bucket([s], "fp64")) == hit
+    assert cache.get(autotune.bucket([s], "fp64", 0)) == hit
