@@ -70,6 +70,13 @@ __global__ __launch_bounds__(kChunk) void k_control(Dev d, Model m, int mode) {
     SysCtl& c = d.ctl[s];
     if (c.done) return;
     const SysDesc& S = d.sys[s];
+    if (S.n_sites == 0) {  // an empty slot evaluates nothing and counts nothing
+        if (threadIdx.x == 0) {
+            c.done = 1;
+            c.converged = 1;
+        }
+        return;
+    }
     double e = 0.0, fm = 0.0, fv = 0.0, ff = 0.0, vv = 0.0, sx = 0.0;
     for (int k = threadIdx.x; k < S.n_chunks; k += blockDim.x) {
         const double* P = d.part + (int64_t)(S.chunk_first + k) * kNPart;
