@@ -343,7 +343,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     P->o_qr = take(sizeof(double) * 3 * N);
     P->o_sref = take(sizeof(double) * N);
     P->o_emit = take(sizeof(double) * N);
-    P->o_srec = take(sizeof(double) * kSRec * N);
+    P->o_srec = take(mom_elt * kSRec * N);  // stored in the moments' precision
     P->o_bond = take(sizeof(int) * N * p.bond_max);
     P->o_nbond = take(sizeof(int) * N);
     P->o_part = take(sizeof(double) * kNPart * P->chunks.size());
@@ -444,7 +444,7 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.qrz = qr + 2 * N;
     D.sref = (double*)(w + P->o_sref);
     D.emit = (double*)(w + P->o_emit);
-    D.srec = (double*)(w + P->o_srec);
+    D.srec = (void*)(w + P->o_srec);
     D.bond = (int*)(w + P->o_bond);
     D.nbond = (int*)(w + P->o_nbond);
     D.part = (double*)(w + P->o_part);

@@ -397,13 +397,14 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
             const double w = occ_partial(ti) ? xi : 1.0;
             const double p1 = occ_p1(ti, xi);
             const int s1 = occ_sp1(ti), s0 = occ_sp0(ti);
-            double* R = d.srec + (int64_t)i * kSRec;
-            R[0] = w * A;
-            R[1] = w * B;
-            R[2] = d.emit[i];
-            for (int k = 0; k < 3; ++k) R[3 + k] = p1 * m.a4[k][s1] + (1.0 - p1) * m.a4[k][s0];
-            R[6] = th;
-            R[7] = 0.0;
+            // (kept in the moments' precision: FP32 in the mixed variant)
+            T* R = (T*)d.srec + (int64_t)i * kSRec;
+            R[0] = (T)(w * A);
+            R[1] = (T)(w * B);
+            R[2] = (T)d.emit[i];
+            for (int k = 0; k < 3; ++k) R[3 + k] = (T)(p1 * m.a4[k][s1] + (1.0 - p1) * m.a4[k][s0]);
+            R[6] = (T)th;
+            R[7] = T(0);
         }
     }
 }
@@ -468,15 +469,33 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
 #pragma unroll
                 for (int e = 0; e < Vec16<T>::n; ++e) mq[v * Vec16<T>::n + e] = b.v[e];
             }
-            const double2* R = (const double2*)(d.srec + (int64_t)j * kSRec);
-            const double2 r01 = R[0], r23 = R[1], r45 = R[2];
-            const double Aj = r01.x, Bj = r01.y, bj = r23.x;
-            const double ampA[3] = {r23.y, r45.x, r45.y};
+            double Aj, Bj, bj, ampA[3], th_j;
+            if constexpr (sizeof(T) == sizeof(double)) {
+                const double2* R = (const double2*)((const double*)d.srec + (int64_t)j * kSRec);
+                const double2 r01 = R[0], r23 = R[1], r45 = R[2];
+                Aj = r01.x;
+                Bj = r01.y;
+                bj = r23.x;
+                ampA[0] = r23.y;
+                ampA[1] = r45.x;
+                ampA[2] = r45.y;
+                th_j = site_T ? R[3].x : 1.0;
+            } else {
+                const float4* R = (const float4*)((const float*)d.srec + (int64_t)j * kSRec);
+                const float4 r0 = R[0], r1 = R[1];
+                Aj = r0.x;
+                Bj = r0.y;
+                bj = r0.z;
+                ampA[0] = r0.w;
+                ampA[1] = r1.x;
+                ampA[2] = r1.y;
+                th_j = r1.z;
+            }
             const double a1 = ampA[i1];
             const double a0 = i0 < 3 ? ampA[i0] : 0.0;
             const double aij = pi1 * a1 + (1.0 - pi1) * a0;
             // the pair term sits half in each end's share: weight (theta_i + theta_j) / 2
-            const double tij = site_T ? 0.5 * (th_i + R[3].x) : 1.0;
+            const double tij = site_T ? 0.5 * (th_i + th_j) : 1.0;
             const double ahat = tij * (part_i ? a1 : aij);
             const double dadx = mob_i ? tij * (a1 - a0) : 0.0;
             const double hA = Ahi * bj + Aj * bhat_i;

@@ -118,7 +118,7 @@ struct Dev {
     void* dblk;   // [pair][2] density pair (<f>, f0) (T)
     double *G, *Ahat, *Bhat;
     double* emit;  // density emitted by each site, b_i (refreshed when x changes)
-    double* srec;  // per-site record read by the force gather, kSRec doubles per site
+    void* srec;    // per-site record read by the force gather, kSRec values of the moment type
     double *vx, *vy, *vz, *vs;
     double *qrx, *qry, *qrz, *sref;
     int *bond, *nbond;
