@@ -254,6 +254,7 @@ def main():
                    "precision": "fp64", "launch": "eager with per-kernel HIP events"},
         "site_steps_per_s": site_steps,
         "evals_in_timed_steps": evals,
+        "list_builds_in_timed_steps": int(sc[mxe.S_REBUILDS]),
         "pairs_per_eval": pair_evals / max(evals, 1),
         "status": status,
         "roofline": roofline,

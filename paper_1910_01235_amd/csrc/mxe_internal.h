@@ -48,6 +48,9 @@ struct SysCtl {
     double fire_dt, fire_alpha;
     double c_keep, mix_v, mix_f;
     unsigned long long sigmax_bits;
+    // largest squared displacement and largest widening (sigma - sigma_build, at
+    // least 0) of any site since the last build, as bits of non-negative doubles
+    unsigned long long drift_bits, widen_bits;
     double dt_master;
     int npos, k, done, converged, updates, evals;
     int rebuild, n_rebuilds, total_evals;

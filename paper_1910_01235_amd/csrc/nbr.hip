@@ -4,13 +4,14 @@
 // |rbar| < r_c + 3 s (the farthest node of the rule sits 3 s from the mean).
 // The list holds every pair with |rbar| < r_c + 3 s_build + skin, where s_build
 // uses both widths at the time of the build. The pair stays listed while
-// 2 max|dq| + 3 sqrt(2) max(sigma - sigma_build) <= skin, since
-// s <= s_build + sqrt(2) max(sigma - sigma_build); each site checks its own share
-// (|dq| <= skin/4, 3 sqrt(2) (sigma - sigma_build) <= skin/2) and requests a
-// rebuild of its system otherwise. Cells are as wide as the largest radius
-// allowed by sigma_cap.
+// 2 max|dq| + 3 sqrt(2) max(sigma - sigma_build, 0) <= skin over the system's
+// sites, since |rbar| loses at most |dq_i| + |dq_j| and
+// s <= s_build + sqrt(2) max(sigma - sigma_build, 0). The FIRE update records both
+// maxima; the build runs when their sum leaves the skin. Cells are as wide as the
+// largest radius allowed by sigma_cap.
 //
 // Build chain per system (each kernel skips systems whose rebuild flag is 0):
+//   k_build_check  per system: raise the flag when the lists may miss a pair
 //   k_bin        cell of each site and its slot in the cell (atomic count)
 //   k_cell_scan  per system: cell offsets (exclusive scan of the counts)
 //   k_fill       place each site in its cell (order within a cell is not
@@ -100,6 +101,8 @@ __global__ void k_sys_init(Dev d) {
     if (d.sys[s].force_build) {
         c.rebuild = 2;
         c.n_pairs = 0;
+        c.drift_bits = 0ull;
+        c.widen_bits = 0ull;
     }
     c.status = 0;
     c.n_rebuilds = 0;
@@ -672,6 +675,15 @@ __global__ __launch_bounds__(kChunk) void k_pid_remap(Dev d) {
     }
 }
 
+__global__ void k_build_check(Dev d, Model m) {
+    const int s = gtid();
+    if (s >= d.n_sys) return;
+    SysCtl& c = d.ctl[s];
+    const double drift = __longlong_as_double((long long)c.drift_bits);
+    const double widen = __longlong_as_double((long long)c.widen_bits);
+    if (2.0 * sqrt(drift) + 3.0 * sqrt(2.0) * widen > m.skin) c.rebuild = 1;
+}
+
 __global__ void k_build_done(Dev d) {
     const int s = gtid();
     if (s >= d.n_sys) return;
@@ -679,6 +691,8 @@ __global__ void k_build_done(Dev d) {
     if (!c.rebuild) return;
     c.n_rebuilds += 1;
     c.rebuild = 0;
+    c.drift_bits = 0ull;
+    c.widen_bits = 0ull;
     d.scalars[(int64_t)s * MXE_NSCALARS + MXE_S_PAIRS] = (double)c.n_pairs;
     d.scalars[(int64_t)s * MXE_NSCALARS + MXE_S_REBUILDS] = (double)c.n_rebuilds;
 }
@@ -690,6 +704,7 @@ int row_pow2(int K) {
 }
 
 void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s) {
+    k_build_check<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d, m);
     k_bin<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_fill<<<d.n_chunks, kChunk, 0, s>>>(d);

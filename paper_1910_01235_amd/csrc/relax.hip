@@ -153,8 +153,9 @@ void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s) {
     k_control<<<d.n_sys, kChunk, 0, s>>>(d, m, mode);
 }
 
-// FIRE velocity mixing and position/width update; flags a list rebuild when a
-// site leaves its skin budget and records the running largest width.
+// FIRE velocity mixing and position/width update; records the running largest
+// width, and the largest displacement and widening since the last build, from
+// which the next build decides whether the lists still hold.
 __global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
     __shared__ double lds[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
     const int i = ch.start + threadIdx.x;
     const double dt = c.fire_dt, mv = c.mix_v, mf = c.mix_f;
     const bool keep = c.c_keep != 0.0;
-    double sg_new = 0.0;
+    double sg_new = 0.0, drift = 0.0, widen = 0.0;
     if (i < ch.end) {
         const double f[4] = {d.fx[i], d.fy[i], d.fz[i], d.fs[i]};
         double* v[4] = {d.vx + i, d.vy + i, d.vz + i, d.vs + i};
@@ -183,14 +184,17 @@ __global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
         }
         if (sg_new > m.sigma_cap) atomicOr(&c.status, MXE_STAT_SIGMA_CAP);
         const double dx = d.qx[i] - d.qrx[i], dy = d.qy[i] - d.qry[i], dz = d.qz[i] - d.qrz[i];
-        const double quarter = 0.25 * m.skin;
-        const bool moved = dx * dx + dy * dy + dz * dz > quarter * quarter;
-        const bool widened = 3.0 * sqrt(2.0) * (sg_new - d.sref[i]) > 0.5 * m.skin;
-        if (moved || widened) c.rebuild = 1;
+        drift = dx * dx + dy * dy + dz * dz;
+        widen = fmax(sg_new - d.sref[i], 0.0);
     }
     const double mx = block_max(sg_new, lds);
-    if (threadIdx.x == 0)
+    const double md = block_max(drift, lds);
+    const double mw = block_max(widen, lds);
+    if (threadIdx.x == 0) {
         atomicMax(&c.sigmax_bits, (unsigned long long)__double_as_longlong(mx));
+        atomicMax(&c.drift_bits, (unsigned long long)__double_as_longlong(md));
+        atomicMax(&c.widen_bits, (unsigned long long)__double_as_longlong(mw));
+    }
 }
 
 void launch_update(const Dev& d, const Model& m, hipStream_t s) {
