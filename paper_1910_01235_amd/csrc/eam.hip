@@ -355,10 +355,17 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
         const int* row = d.nbr + (int64_t)i * K;
         const int* prow = d.pid + (int64_t)i * K;
         double rb = 0.0, r0 = 0.0;
-#pragma unroll 2
+        int jn = 0, pn = -1;  // next entry, loaded one iteration ahead
+        if (sub < cnt) {
+            jn = row[sub];
+            pn = prow[sub];
+        }
         for (int k = sub; k < cnt; k += kLPS) {
-            const int j = row[k];
-            const int p = prow[k];
+            const int j = jn, p = pn;
+            if (k + kLPS < cnt) {
+                jn = row[k + kLPS];
+                pn = prow[k + kLPS];
+            }
             if (p < 0) continue;
             const double bj = d.emit[j];
             rb += bj * (double)dblk[2 * (int64_t)p];
@@ -458,9 +465,19 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
         const int* row = d.nbr + (int64_t)i * K;
         const int* prow = d.pid + (int64_t)i * K;
         double fx = 0.0, fy = 0.0, fz = 0.0, fsg = 0.0, mu = 0.0, ep = 0.0;
+        // the next entry's (j, pair id) load while this entry's block and record
+        // are fetched, so an iteration waits for one round trip instead of three
+        int jn = 0, pn = -1;
+        if (es < cnt) {
+            jn = row[es];
+            pn = prow[es];
+        }
         for (int k = es; k < cnt; k += kLPS / kQ) {
-            const int j = row[k];
-            const int p = prow[k];
+            const int j = jn, p = pn;
+            if (k + kLPS / kQ < cnt) {
+                jn = row[k + kLPS / kQ];
+                pn = prow[k + kLPS / kQ];
+            }
             if (p < 0) continue;
             T mq[4];
 #pragma unroll
