@@ -144,6 +144,15 @@ __device__ inline double theta_at(const Dev& d, const SysDesc& S, int i) {
     return d.T_site != nullptr ? S.T / d.T_site[i] : 1.0;
 }
 
+// Running maximum of non-negative doubles kept as their bit patterns (ordered
+// like the values). The maxima only grow, so a value that does not exceed a
+// (possibly stale) read of the current one needs no atomic: one block in many
+// contends for the line instead of all of them.
+__device__ inline void raise_max(unsigned long long* bits, double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b > *(volatile unsigned long long*)bits) atomicMax(bits, b);
+}
+
 // is mobile site i (of type t) a reservoir site of the given kind?
 __device__ inline bool held(const Dev& d, int i, int t, int kind) {
     return d.res != nullptr && d.res[i] == kind && occ_mobile(t);

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kChunk) void k_site_init(Dev d, Model m) {
     if (threadIdx.x == 0) {
         double mx = red[0];
         for (int w = 1; w < kChunk / kWave; ++w) mx = fmax(mx, red[w]);
-        atomicMax(&d.ctl[ch.sys].sigmax_bits, (unsigned long long)__double_as_longlong(mx));
+        raise_max(&d.ctl[ch.sys].sigmax_bits, mx);
     }
 }
 

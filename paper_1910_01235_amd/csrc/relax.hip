@@ -191,9 +191,9 @@ __global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
     const double md = block_max(drift, lds);
     const double mw = block_max(widen, lds);
     if (threadIdx.x == 0) {
-        atomicMax(&c.sigmax_bits, (unsigned long long)__double_as_longlong(mx));
-        atomicMax(&c.drift_bits, (unsigned long long)__double_as_longlong(md));
-        atomicMax(&c.widen_bits, (unsigned long long)__double_as_longlong(mw));
+        raise_max(&c.sigmax_bits, mx);
+        raise_max(&c.drift_bits, md);
+        raise_max(&c.widen_bits, mw);
     }
 }
 
