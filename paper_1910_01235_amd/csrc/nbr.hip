@@ -318,6 +318,9 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
     const int K = d.K;
     const double reach = m.r_c + m.skin + 1e-6;
     const double ib0 = 1.0 / S.box[0], ib1 = 1.0 / S.box[1], ib2 = 1.0 / S.box[2];
+    // minimum image: periodic axes subtract box * rint(d / box), open axes nothing
+    const double pb0 = S.periodic[0] ? S.box[0] : 0.0, pb1 = S.periodic[1] ? S.box[1] : 0.0,
+                 pb2 = S.periodic[2] ? S.box[2] : 0.0;
     int up_sum = 0;
     bool over = false;
     const double smax = __longlong_as_double((long long)d.ctl[s].sigmax_bits);
@@ -373,30 +376,34 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             constexpr int kCand = 4;  // candidates per lane and pass (independent loads)
             for (int base = t0; base < t1; base += kWave * kCand) {
+                // Three phases, so that all of a lane's candidate loads are in
+                // flight at once: table entries (a lane past the tile's end
+                // rereads its last entry and is masked), then every index and
+                // record load, then the branch-free radius tests.
+                int pos[kCand];
+#pragma unroll
+                for (int u = 0; u < kCand; ++u) pos[u] = ctab[min(base + u * kWave + lane, t1 - 1) - t0];
+                int jt[kCand];
+                double4 rj[kCand];
+#pragma unroll
+                for (int u = 0; u < kCand; ++u) {
+                    jt[u] = d.cell_sites[pos[u]];
+                    rj[u] = d.cell_rec[pos[u]];
+                }
                 int jc[kCand];
                 bool okc[kCand];
 #pragma unroll
                 for (int u = 0; u < kCand; ++u) {
-                    const int e = base + u * kWave + lane;
-                    jc[u] = -1;
-                    bool ok = false;
-                    if (e < t1) {
-                        const int pos = ctab[e - t0];
-                        const int jt = d.cell_sites[pos];
-                        const int j = jt >> 2;
-                        jc[u] = j;
-                        if (j != i && pair_cls(ti, jt & 3) >= 0) {
-                            const double4 rj = d.cell_rec[pos];
-                            double dx = rj.x - qi0, dy = rj.y - qi1, dz = rj.z - qi2;
-                            if (S.periodic[0]) dx -= S.box[0] * rint(dx * ib0);
-                            if (S.periodic[1]) dy -= S.box[1] * rint(dy * ib1);
-                            if (S.periodic[2]) dz -= S.box[2] * rint(dz * ib2);
-                            const float sf = __builtin_sqrtf((float)(si2 + rj.w * rj.w));
-                            const double rl = reach + 3.0 * (double)sf;
-                            ok = dx * dx + dy * dy + dz * dz < rl * rl;
-                        }
-                    }
-                    okc[u] = ok;
+                    const int j = jt[u] >> 2;
+                    double dx = rj[u].x - qi0, dy = rj[u].y - qi1, dz = rj[u].z - qi2;
+                    dx -= pb0 * rint(dx * ib0);
+                    dy -= pb1 * rint(dy * ib1);
+                    dz -= pb2 * rint(dz * ib2);
+                    const float sf = __builtin_sqrtf((float)(si2 + rj[u].w * rj[u].w));
+                    const double rl = reach + 3.0 * (double)sf;
+                    jc[u] = j;
+                    okc[u] = (base + u * kWave + lane < t1) & (j != i) & (pair_cls(ti, jt[u] & 3) >= 0) &
+                             (dx * dx + dy * dy + dz * dz < rl * rl);
                 }
 #pragma unroll
                 for (int u = 0; u < kCand; ++u) {
