@@ -44,10 +44,14 @@ struct mxe_plan {
     void* tables_ws = nullptr;   // workspace that holds the uploaded tables
     std::vector<SysDesc> sys;
     std::vector<Chunk> chunks, pchunks;
+    // cells in use: entry 0 holds their count, entries 1.. (system, global cell);
+    // the count lives in device memory so that a captured graph stays valid
+    // when slots are rebound
+    std::vector<int2> acells;
     int64_t n_sites = 0, n_cells = 0, pair_cap_total = 0;
     // workspace layout (byte offsets)
     size_t o_sys, o_ctl, o_chunks, o_pchunks, o_site_sys, o_cell_count, o_cell_start, o_cell_sites, o_cell_rec;
-    size_t o_cell_of, o_slot_of, o_chunk_up, o_chunk_off;
+    size_t o_cell_of, o_slot_of, o_chunk_up, o_chunk_off, o_acell;
     size_t o_nbr, o_cnt, o_lo, o_pid, o_hoff, o_pi, o_pj, o_pnew, o_fblk, o_dblk, o_G, o_A, o_B;
     size_t o_v, o_qr, o_sref, o_emit, o_srec, o_bond, o_nbond, o_part;
     size_t ws_bytes = 0;
@@ -110,6 +114,12 @@ void bind_slot(mxe_plan* P, int s, const mxe_system& ms) {
     P->systems[s] = ms;
     P->dirty[s] = 1;
     P->tables_dirty = true;
+    // cells in use, slot by slot (the neighbour search runs one block per entry)
+    P->acells.assign(1, make_int2(0, 0));
+    for (int t = 0; t < (int)P->sys.size(); ++t)
+        for (int64_t c = 0; c < P->sys[t].n_cells; ++c)
+            P->acells.push_back(make_int2(t, (int)(P->sys[t].cell_off + c)));
+    P->acells[0].x = (int)P->acells.size() - 1;
 }
 
 }  // namespace
@@ -326,6 +336,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     P->o_slot_of = take(sizeof(int) * N);
     P->o_chunk_up = take(sizeof(int) * P->chunks.size());
     P->o_chunk_off = take(sizeof(int) * P->chunks.size());
+    P->o_acell = take(sizeof(int2) * (P->n_cells + 1));
     P->o_nbr = take(sizeof(int) * N * p.k_max);
     P->o_cnt = take(sizeof(int) * N);
     P->o_lo = take(sizeof(int) * N);
@@ -420,6 +431,7 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.slot_of = (int*)(w + P->o_slot_of);
     D.chunk_up = (int*)(w + P->o_chunk_up);
     D.chunk_off = (int*)(w + P->o_chunk_off);
+    D.acell = (int2*)(w + P->o_acell);
     D.nbr = (int*)(w + P->o_nbr);
     D.nbr_cnt = (int*)(w + P->o_cnt);
     D.nbr_lo = (int*)(w + P->o_lo);
@@ -473,6 +485,8 @@ mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, bool bonds) {
         HIP_OK(hipMemcpyAsync(d.chunks, P->chunks.data(), sizeof(Chunk) * P->chunks.size(),
                               hipMemcpyHostToDevice, s));
         HIP_OK(hipMemcpyAsync(d.pchunks, P->pchunks.data(), sizeof(Chunk) * P->pchunks.size(),
+                              hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(d.acell, P->acells.data(), sizeof(int2) * P->acells.size(),
                               hipMemcpyHostToDevice, s));
         P->tables_dirty = false;
         P->tables_ws = (void*)d.sys;

@@ -47,7 +47,6 @@ struct SysDesc {
 struct SysCtl {
     double fire_dt, fire_alpha;
     double c_keep, mix_v, mix_f;
-    unsigned long long sigmax_bits;
     // largest squared displacement and largest widening (sigma - sigma_build, at
     // least 0) of any site since the last build, as bits of non-negative doubles
     unsigned long long drift_bits, widen_bits;
@@ -114,6 +113,7 @@ struct Dev {
     double4* cell_rec; // (qx, qy, qz, sigma) of the same entries
     int *cell_of, *slot_of;
     int *chunk_up, *chunk_off;
+    int2* acell;       // [0].x: number of cells in use; [1 + b]: (system, global cell)
     int *nbr, *nbr_cnt, *nbr_lo, *pid, *half_off;
     int *pair_i, *pair_j;
     int* pnew;         // per pair: its number after the renumbering by geometric class
@@ -194,7 +194,7 @@ __device__ inline int xcd_chunk(int n) {
     const int per = (n + kXcd - 1) / kXcd;
     return (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
 }
-inline int xcd_grid(int n) { return (n + kXcd - 1) / kXcd * kXcd; }
+__host__ __device__ inline int xcd_grid(int n) { return (n + kXcd - 1) / kXcd * kXcd; }
 __device__ inline int gstride() { return gridDim.x * blockDim.x; }
 
 // binary search for the system that owns global index `idx` given an

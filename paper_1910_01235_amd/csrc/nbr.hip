@@ -16,9 +16,10 @@
 //   k_cell_scan  per system: cell offsets (exclusive scan of the counts)
 //   k_fill       place each site in its cell (order within a cell is not
 //                deterministic; rows are sorted afterwards, so nothing depends on it)
-//   k_nbr        one wavefront per site: lanes test the stencil's candidates,
-//                survivors are compacted by ballot and sorted (bitonic, in LDS);
-//                per-chunk count of "upper" neighbours (larger index)
+//   k_nbr        one block per cell in use: the stencil's candidates staged in
+//                LDS, one wave per site tests them; survivors are compacted by
+//                ballot and sorted (bitonic, in registers)
+//   k_chunk_up   per chunk: count of "upper" neighbours (larger index)
 //   k_bonds      per mobile site: same-type sites closer than r_bond (sorted)
 //   k_scan       per system: offsets of the chunks' upper counts; pair count;
 //                clears the cell counts for the next build
@@ -95,7 +96,6 @@ __global__ void k_sys_init(Dev d) {
     const int s = gtid();
     if (s >= d.n_sys) return;
     SysCtl& c = d.ctl[s];
-    c.sigmax_bits = 0ull;
     // A forced system rebuilds everything; otherwise its lists, pair count and
     // any pending rebuild request carry over from the previous call.
     if (d.sys[s].force_build) {
@@ -112,15 +112,13 @@ __global__ void k_sys_init(Dev d) {
     c.k = 0;
 }
 
-// widths and occupancies are checked, and the largest width recorded
+// widths, occupancies, positions and site temperatures are checked
 __global__ __launch_bounds__(kChunk) void k_site_init(Dev d, Model m) {
-    __shared__ double red[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
     const int i = ch.start + threadIdx.x;
-    double sg = 0.0;
     int st = 0;
     if (i < ch.end) {
-        sg = d.sigma[i];
+        const double sg = d.sigma[i];
         double xi = d.x[i];
         if (held(d, i, d.type[i], MXE_RES_FIX_X)) {  // held fraction (set at the call start)
             xi = d.res_val[i];
@@ -131,20 +129,9 @@ __global__ __launch_bounds__(kChunk) void k_site_init(Dev d, Model m) {
         if (!isfinite(xi) || xi < -1e-12 || xi > 1.0 + 1e-12) st |= MXE_STAT_X_RANGE;
         if (!isfinite(d.qx[i]) || !isfinite(d.qy[i]) || !isfinite(d.qz[i])) st |= MXE_STAT_NONFINITE;
         if (d.T_site != nullptr && !(d.T_site[i] > 0.0 && isfinite(d.T_site[i]))) st |= MXE_STAT_TEMP;
-        if (!(sg > 0.0)) sg = 0.0;
         d.emit[i] = mixval(m.b4, d.type[i], xi);
     }
     if (st) atomicOr(&d.ctl[ch.sys].status, st);
-    double v = sg;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double mx = red[0];
-        for (int w = 1; w < kChunk / kWave; ++w) mx = fmax(mx, red[w]);
-        raise_max(&d.ctl[ch.sys].sigmax_bits, mx);
-    }
 }
 
 void launch_sys_init(const Dev& d, const Model& m, hipStream_t s) {
@@ -287,173 +274,220 @@ __device__ inline void wave_sort(int (&v)[E], int lane) {
     }
 }
 
-constexpr int kCandTile = 1024;  // candidate positions staged per wave and pass
+constexpr int kCellTile = 768;  // stencil candidates staged in LDS at a time
 
-// One wavefront per site. Lanes 0-26 each take one stencil cell; a wave scan
-// of the cell counts lays the stencil out as one flat candidate list, whose
-// record positions the stencil lanes write into an LDS table (in tiles of
-// kCandTile). All lanes then walk the table in strides of 64, testing each
-// candidate against the pair's list radius; hits are compacted by ballot into
-// an LDS row, which is sorted in registers (E entries per lane).
+// One block per cell in use. Every site of a cell has the same 27-cell stencil,
+// so the block stages the stencil's candidates (site index and type, position
+// and width) in LDS, kCellTile at a time, and its waves test the cell's sites
+// against them, one site per wave and round. Per candidate and site the test
+// is the list-radius test below; hits are compacted by ballot into an LDS row,
+// which is sorted in registers (E entries per lane) and written out.
 // The radius test is a superset test: the minimum image uses the reciprocal
 // box length and s_ij an FP32 square root, and the radius is padded by 1e-6 A,
 // so every pair the exact test admits is admitted (an extra pair whose nodes
-// all lie beyond r_c contributes exact zeros).
+// all lie beyond r_c contributes exact zeros). Rows are sorted, so they do not
+// depend on the order of the sites within a cell.
 template <int E>
 __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
     constexpr int K2 = kWave * E;
     constexpr int kWaves = kChunk / kWave;
     __shared__ int rows[kWaves][K2];
-    __shared__ int cand[kWaves][kCandTile];
-    __shared__ int wave_up[kWaves];
-    const int cb = xcd_chunk(d.n_chunks);
-    if (cb >= d.n_chunks) return;
-    const Chunk ch = d.chunks[cb];
-    const int s = ch.sys;
+    __shared__ int tj[kCellTile];        // 4 * site index + type
+    __shared__ double4 trec[kCellTile];  // position and width
+    __shared__ int st_start[27], st_pre[28];  // stencil cells: first record, prefix of counts
+    __shared__ int sh_center;                 // prefix of the cell itself in the stencil
+    // The grid covers every cell the plan can hold; the cells in use are
+    // dealt to the XCDs by their count, read from the table.
+    const int na = d.acell[0].x;
+    if ((int)blockIdx.x >= xcd_grid(na)) return;
+    const int b = xcd_chunk(na);
+    if (b >= na) return;
+    const int2 ac = d.acell[1 + b];
+    const int s = ac.x, g = ac.y;
     if (!d.ctl[s].rebuild) return;
+    const int nsite = d.cell_count[g];
+    if (nsite == 0) return;  // every exit above is uniform over the block
     const SysDesc& S = d.sys[s];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int* row = rows[wave];
-    int* ctab = cand[wave];
-    const int K = d.K;
-    const double reach = m.r_c + m.skin + 1e-6;
-    const double ib0 = 1.0 / S.box[0], ib1 = 1.0 / S.box[1], ib2 = 1.0 / S.box[2];
-    // minimum image: periodic axes subtract box * rint(d / box), open axes nothing
-    const double pb0 = S.periodic[0] ? S.box[0] : 0.0, pb1 = S.periodic[1] ? S.box[1] : 0.0,
-                 pb2 = S.periodic[2] ? S.box[2] : 0.0;
-    int up_sum = 0;
-    bool over = false;
-    const double smax = __longlong_as_double((long long)d.ctl[s].sigmax_bits);
-    for (int i = ch.start + wave; i < ch.end; i += kWaves) {
-        const double qi0 = d.qx[i], qi1 = d.qy[i], qi2 = d.qz[i];
-        const double si2 = d.sigma[i] * d.sigma[i];
-        const double rmax = reach + 3.0 * sqrt(si2 + smax * smax) + 1e-6;
-        const double rmax2 = rmax * rmax;
-        const int ti = d.type[i];
-        const int c[3] = {cell_coord(qi0, S.box[0], S.cell_w[0], S.nc[0], S.periodic[0]),
-                          cell_coord(qi1, S.box[1], S.cell_w[1], S.nc[1], S.periodic[1]),
-                          cell_coord(qi2, S.box[2], S.cell_w[2], S.nc[2], S.periodic[2])};
-        int cnt_c = 0, start_c = 0;
+    if (wave == 0) {
+        const int lc = g - (int)S.cell_off;
+        const int c[3] = {lc / (S.nc[1] * S.nc[2]), (lc / S.nc[2]) % S.nc[1], lc % S.nc[2]};
+        int cnt = 0, start = 0;
+        bool center = false;
         if (lane < 27) {
             const int64_t cell = stencil_lane_cell(S, c, lane);
-            // skip a stencil cell whose nearest face lies beyond every radius a
-            // pair of site i can have (for periodic axes with fewer than three
-            // cells the stencil repeats cells, and that axis is not culled)
-            const int o[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
-            const double u[3] = {qi0, qi1, qi2};
-            double gap2 = 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (o[a] == 0 || (S.periodic[a] && S.nc[a] < 3)) continue;
-                double v = u[a];
-                if (S.periodic[a]) v -= S.box[a] * floor(v / S.box[a]);
-                const double g = o[a] > 0 ? (c[a] + 1) * S.cell_w[a] - v : v - c[a] * S.cell_w[a];
-                if (g > 0.0) gap2 += g * g;
-            }
-            if (cell >= 0 && gap2 < rmax2) {
-                cnt_c = d.cell_count[cell];
-                start_c = d.cell_start[cell];
+            if (cell >= 0) {
+                cnt = d.cell_count[cell];
+                start = d.cell_start[cell];
+                center = cell == g;
             }
         }
-        // inclusive wave scan of the counts (lanes >= 27 hold zero)
-        int incl = cnt_c;
+        int incl = cnt;  // inclusive wave scan of the counts (lanes >= 27 hold zero)
 #pragma unroll
         for (int o = 1; o < 32; o <<= 1) {
             const int u = __shfl_up(incl, o);
             if (lane >= o) incl += u;
         }
-        const int pre = incl - cnt_c;
-        const int total = __shfl(incl, 31);
+        if (lane < 27) {
+            st_start[lane] = start;
+            st_pre[lane] = incl - cnt;
+        }
+        if (lane == 26) st_pre[27] = incl;
+        // the cell itself is one of the stencil cells (the first offset reaching it)
+        const int cl = __ffsll((long long)__ballot(center)) - 1;
+        const int cpre = __shfl(incl - cnt, cl);
+        if (lane == 0) sh_center = cpre;
+    }
+    __syncthreads();
+    const int T = st_pre[27];
+    const int ntiles = (T + kCellTile - 1) / kCellTile;
+    const double reach = m.r_c + m.skin + 1e-6;
+    const double ib0 = 1.0 / S.box[0], ib1 = 1.0 / S.box[1], ib2 = 1.0 / S.box[2];
+    // minimum image: periodic axes subtract box * rint(d / box), open axes nothing
+    const double pb0 = S.periodic[0] ? S.box[0] : 0.0, pb1 = S.periodic[1] ? S.box[1] : 0.0,
+                 pb2 = S.periodic[2] ? S.box[2] : 0.0;
+    const int K = d.K;
+    int* row = rows[wave];
+    bool over = false;
+
+    // stage candidates [t0, t1) of the stencil into the tile (whole block); a
+    // thread past t1 loads candidate t0 (always valid) and stores nothing
+    auto stage = [&](int t0, int t1) {
+        constexpr int kPer = kCellTile / kChunk;
+        int pos[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = t0 + u * kChunk + (int)threadIdx.x;
+            const int ec = e < t1 ? e : t0;
+            int L = 0;  // stencil cell holding candidate ec: last L with st_pre[L] <= ec
+#pragma unroll
+            for (int step = 16; step > 0; step >>= 1)
+                if (L + step < 27 && st_pre[L + step] <= ec) L += step;
+            pos[u] = st_start[L] + (ec - st_pre[L]);
+        }
+        int jt[kPer];
+        double4 rj[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            jt[u] = d.cell_sites[pos[u]];
+            rj[u] = d.cell_rec[pos[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = u * kChunk + (int)threadIdx.x;
+            if (t0 + e < t1) {
+                tj[e] = jt[u];
+                trec[e] = rj[u];
+            }
+        }
+    };
+
+    if (ntiles == 1) {
+        stage(0, T);
+        __syncthreads();
+    }
+    for (int r0 = 0; r0 < nsite; r0 += kWaves) {
+        const int k = r0 + wave;  // this wave's site of the cell in this round
+        const bool has = k < nsite;
+        int i = 0, ti = 0;
+        double qi0 = 0.0, qi1 = 0.0, qi2 = 0.0, si2 = 0.0;
+        if (has) {
+            int jt;
+            double4 ri;
+            if (ntiles == 1) {  // the cell's own records lie in the staged stencil
+                jt = tj[sh_center + k];
+                ri = trec[sh_center + k];
+            } else {
+                const int pos = d.cell_start[g] + k;
+                jt = d.cell_sites[pos];
+                ri = d.cell_rec[pos];
+            }
+            i = jt >> 2;
+            ti = jt & 3;
+            qi0 = ri.x;
+            qi1 = ri.y;
+            qi2 = ri.z;
+            si2 = ri.w * ri.w;
+        }
         int n = 0;
-        for (int t0 = 0; t0 < total; t0 += kCandTile) {
-            const int t1 = min(total, t0 + kCandTile);
-            // stencil lanes write the record positions of their cell's part of the tile
-            if (cnt_c > 0) {
-                const int a = max(pre, t0), b = min(pre + cnt_c, t1);
-                for (int e = a; e < b; ++e) ctab[e - t0] = start_c + (e - pre);
+        for (int t = 0; t < ntiles; ++t) {
+            const int t0 = t * kCellTile, t1 = min(T, t0 + kCellTile);
+            if (ntiles > 1) {
+                __syncthreads();  // every wave is done with the previous tile
+                stage(t0, t1);
+                __syncthreads();
+            }
+            if (!has) continue;
+            for (int base = 0; base < t1 - t0; base += kWave) {
+                const int e = base + lane;
+                const bool in = e < t1 - t0;
+                const int jt = tj[in ? e : 0];
+                const double4 rj = trec[in ? e : 0];
+                const int j = jt >> 2;
+                double dx = rj.x - qi0, dy = rj.y - qi1, dz = rj.z - qi2;
+                dx -= pb0 * rint(dx * ib0);
+                dy -= pb1 * rint(dy * ib1);
+                dz -= pb2 * rint(dz * ib2);
+                const float sf = __builtin_sqrtf((float)(si2 + rj.w * rj.w));
+                const double rl = reach + 3.0 * (double)sf;
+                const bool ok = in & (j != i) & (pair_cls(ti, jt & 3) >= 0) &
+                                (dx * dx + dy * dy + dz * dz < rl * rl);
+                const unsigned long long mask = __ballot(ok);
+                const int pos = n + __popcll(mask & __lanemask_lt());
+                if (ok && pos < K2) row[pos] = j;
+                n += __popcll(mask);
+            }
+        }
+        if (has) {
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            if (n > K) over = true;
+            const int nk = min(n, K);
+            int v[E];
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int t = r * kWave + lane;
+                v[r] = t < min(n, K2) ? row[t] : 0x7fffffff;
+            }
+            wave_sort<E>(v, lane);
+            int lo = 0;
+            int* out = d.nbr + (int64_t)i * K;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int t = r * kWave + lane;
+                if (t < nk) {
+                    out[t] = v[r];
+                    lo += (v[r] < i);
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) lo += __shfl_xor(lo, o);
+            if (lane == 0) {
+                d.nbr_cnt[i] = nk;
+                d.nbr_lo[i] = lo;
             }
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            constexpr int kCand = 4;  // candidates per lane and pass (independent loads)
-            for (int base = t0; base < t1; base += kWave * kCand) {
-                // Three phases, so that all of a lane's candidate loads are in
-                // flight at once: table entries (a lane past the tile's end
-                // rereads its last entry and is masked), then every index and
-                // record load, then the branch-free radius tests.
-                int pos[kCand];
-#pragma unroll
-                for (int u = 0; u < kCand; ++u) pos[u] = ctab[min(base + u * kWave + lane, t1 - 1) - t0];
-                int jt[kCand];
-                double4 rj[kCand];
-#pragma unroll
-                for (int u = 0; u < kCand; ++u) {
-                    jt[u] = d.cell_sites[pos[u]];
-                    rj[u] = d.cell_rec[pos[u]];
-                }
-                int jc[kCand];
-                bool okc[kCand];
-#pragma unroll
-                for (int u = 0; u < kCand; ++u) {
-                    const int j = jt[u] >> 2;
-                    double dx = rj[u].x - qi0, dy = rj[u].y - qi1, dz = rj[u].z - qi2;
-                    dx -= pb0 * rint(dx * ib0);
-                    dy -= pb1 * rint(dy * ib1);
-                    dz -= pb2 * rint(dz * ib2);
-                    const float sf = __builtin_sqrtf((float)(si2 + rj[u].w * rj[u].w));
-                    const double rl = reach + 3.0 * (double)sf;
-                    jc[u] = j;
-                    okc[u] = (base + u * kWave + lane < t1) & (j != i) & (pair_cls(ti, jt[u] & 3) >= 0) &
-                             (dx * dx + dy * dy + dz * dz < rl * rl);
-                }
-#pragma unroll
-                for (int u = 0; u < kCand; ++u) {
-                    const unsigned long long mask = __ballot(okc[u]);
-                    const int pos = n + __popcll(mask & __lanemask_lt());
-                    if (okc[u] && pos < K2) row[pos] = jc[u];
-                    n += __popcll(mask);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
-        if (n > K) over = true;
-        const int nk = min(n, K);
-        int v[E];
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int t = r * kWave + lane;
-            v[r] = t < min(n, K2) ? row[t] : 0x7fffffff;
-        }
-        wave_sort<E>(v, lane);
-        int lo = 0;
-        int* out = d.nbr + (int64_t)i * K;
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int t = r * kWave + lane;
-            if (t < nk) {
-                out[t] = v[r];
-                lo += (v[r] < i);
-            }
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) lo += __shfl_xor(lo, o);
-        if (lane == 0) {
-            d.nbr_cnt[i] = nk;
-            d.nbr_lo[i] = lo;
-        }
-        up_sum += nk - lo;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
-    if (lane == 0) {
-        wave_up[wave] = up_sum;
-        if (over) atomicOr(&d.ctl[s].status, MXE_STAT_KMAX);
-    }
+    if (lane == 0 && over) atomicOr(&d.ctl[s].status, MXE_STAT_KMAX);
+}
+
+// Per chunk: the number of pairs its sites own (row entries above the site).
+__global__ __launch_bounds__(kChunk) void k_chunk_up(Dev d) {
+    __shared__ int lds[kChunk / kWave];
+    const Chunk ch = d.chunks[blockIdx.x];
+    if (!d.ctl[ch.sys].rebuild) return;
+    const int i = ch.start + threadIdx.x;
+    int u = i < ch.end ? d.nbr_cnt[i] - d.nbr_lo[i] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = u;
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
-        for (int w = 0; w < kWaves; ++w) t += wave_up[w];
-        d.chunk_up[cb] = t;
+        for (int w = 0; w < kChunk / kWave; ++w) t += lds[w];
+        d.chunk_up[blockIdx.x] = t;
     }
 }
 
@@ -715,11 +749,13 @@ void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s) {
     k_bin<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_fill<<<d.n_chunks, kChunk, 0, s>>>(d);
+    const int gc = xcd_grid((int)d.n_cells);
     switch (row_pow2(d.K)) {
-        case 64: k_nbr<1><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
-        case 128: k_nbr<2><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
-        default: k_nbr<4><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        case 64: k_nbr<1><<<gc, kChunk, 0, s>>>(d, m); break;
+        case 128: k_nbr<2><<<gc, kChunk, 0, s>>>(d, m); break;
+        default: k_nbr<4><<<gc, kChunk, 0, s>>>(d, m); break;
     }
+    k_chunk_up<<<d.n_chunks, kChunk, 0, s>>>(d);
     if (bonds) k_bonds<<<d.n_chunks, kChunk, 0, s>>>(d, m);
     k_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_half<<<d.n_chunks, kChunk, 0, s>>>(d);

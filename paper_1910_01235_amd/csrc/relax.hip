@@ -153,9 +153,9 @@ void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s) {
     k_control<<<d.n_sys, kChunk, 0, s>>>(d, m, mode);
 }
 
-// FIRE velocity mixing and position/width update; records the running largest
-// width, and the largest displacement and widening since the last build, from
-// which the next build decides whether the lists still hold.
+// FIRE velocity mixing and position/width update; records the largest
+// displacement and widening since the last build, from which the next build
+// decides whether the lists still hold.
 __global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
     __shared__ double lds[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
@@ -187,11 +187,9 @@ __global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
         drift = dx * dx + dy * dy + dz * dz;
         widen = fmax(sg_new - d.sref[i], 0.0);
     }
-    const double mx = block_max(sg_new, lds);
     const double md = block_max(drift, lds);
     const double mw = block_max(widen, lds);
     if (threadIdx.x == 0) {
-        raise_max(&c.sigmax_bits, mx);
         raise_max(&c.drift_bits, md);
         raise_max(&c.widen_bits, mw);
     }
