@@ -20,7 +20,7 @@
 //                LDS, one wave per site tests them; survivors are compacted by
 //                ballot and sorted (bitonic, in registers)
 //   k_chunk_up   per chunk: count of "upper" neighbours (larger index)
-//   k_bonds      per mobile site: same-type sites closer than r_bond (sorted)
+//   k_bonds      per mobile site: same-type row entries closer than r_bond (sorted)
 //   k_scan       per system: offsets of the chunks' upper counts; pair count;
 //                clears the cell counts for the next build
 //   k_half       per chunk: offset of each site's first owned pair (each
@@ -275,8 +275,9 @@ __device__ inline void wave_sort(int (&v)[E], int lane) {
 }
 
 constexpr int kCellTile = 768;  // stencil candidates staged in LDS at a time
+constexpr int kNbrGrid = 16384;  // blocks of the neighbour search at most
 
-// One block per cell in use. Every site of a cell has the same 27-cell stencil,
+// One block per cell in use at a time. Every site of a cell has the same 27-cell stencil,
 // so the block stages the stencil's candidates (site index and type, position
 // and width) in LDS, kCellTile at a time, and its waves test the cell's sites
 // against them, one site per wave and round. Per candidate and site the test
@@ -296,181 +297,193 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
     __shared__ double4 trec[kCellTile];  // position and width
     __shared__ int st_start[27], st_pre[28];  // stencil cells: first record, prefix of counts
     __shared__ int sh_center;                 // prefix of the cell itself in the stencil
-    // The grid covers every cell the plan can hold; the cells in use are
-    // dealt to the XCDs by their count, read from the table.
-    const int na = d.acell[0].x;
-    if ((int)blockIdx.x >= xcd_grid(na)) return;
-    const int b = xcd_chunk(na);
-    if (b >= na) return;
-    const int2 ac = d.acell[1 + b];
-    const int s = ac.x, g = ac.y;
-    if (!d.ctl[s].rebuild) return;
-    const int nsite = d.cell_count[g];
-    if (nsite == 0) return;  // every exit above is uniform over the block
-    const SysDesc& S = d.sys[s];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (wave == 0) {
-        const int lc = g - (int)S.cell_off;
-        const int c[3] = {lc / (S.nc[1] * S.nc[2]), (lc / S.nc[2]) % S.nc[1], lc % S.nc[2]};
-        int cnt = 0, start = 0;
-        bool center = false;
-        if (lane < 27) {
-            const int64_t cell = stencil_lane_cell(S, c, lane);
-            if (cell >= 0) {
-                cnt = d.cell_count[cell];
-                start = d.cell_start[cell];
-                center = cell == g;
-            }
-        }
-        int incl = cnt;  // inclusive wave scan of the counts (lanes >= 27 hold zero)
-#pragma unroll
-        for (int o = 1; o < 32; o <<= 1) {
-            const int u = __shfl_up(incl, o);
-            if (lane >= o) incl += u;
-        }
-        if (lane < 27) {
-            st_start[lane] = start;
-            st_pre[lane] = incl - cnt;
-        }
-        if (lane == 26) st_pre[27] = incl;
-        // the cell itself is one of the stencil cells (the first offset reaching it)
-        const int cl = __ffsll((long long)__ballot(center)) - 1;
-        const int cpre = __shfl(incl - cnt, cl);
-        if (lane == 0) sh_center = cpre;
-    }
-    __syncthreads();
-    const int T = st_pre[27];
-    const int ntiles = (T + kCellTile - 1) / kCellTile;
-    const double reach = m.r_c + m.skin + 1e-6;
-    const double ib0 = 1.0 / S.box[0], ib1 = 1.0 / S.box[1], ib2 = 1.0 / S.box[2];
-    // minimum image: periodic axes subtract box * rint(d / box), open axes nothing
-    const double pb0 = S.periodic[0] ? S.box[0] : 0.0, pb1 = S.periodic[1] ? S.box[1] : 0.0,
-                 pb2 = S.periodic[2] ? S.box[2] : 0.0;
-    const int K = d.K;
-    int* row = rows[wave];
-    bool over = false;
-
-    // stage candidates [t0, t1) of the stencil into the tile (whole block); a
-    // thread past t1 loads candidate t0 (always valid) and stores nothing
-    auto stage = [&](int t0, int t1) {
-        constexpr int kPer = kCellTile / kChunk;
-        int pos[kPer];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = t0 + u * kChunk + (int)threadIdx.x;
-            const int ec = e < t1 ? e : t0;
-            int L = 0;  // stencil cell holding candidate ec: last L with st_pre[L] <= ec
-#pragma unroll
-            for (int step = 16; step > 0; step >>= 1)
-                if (L + step < 27 && st_pre[L + step] <= ec) L += step;
-            pos[u] = st_start[L] + (ec - st_pre[L]);
-        }
-        int jt[kPer];
-        double4 rj[kPer];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            jt[u] = d.cell_sites[pos[u]];
-            rj[u] = d.cell_rec[pos[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = u * kChunk + (int)threadIdx.x;
-            if (t0 + e < t1) {
-                tj[e] = jt[u];
-                trec[e] = rj[u];
-            }
-        }
-    };
-
-    if (ntiles == 1) {
-        stage(0, T);
-        __syncthreads();
-    }
-    for (int r0 = 0; r0 < nsite; r0 += kWaves) {
-        const int k = r0 + wave;  // this wave's site of the cell in this round
-        const bool has = k < nsite;
-        int i = 0, ti = 0;
-        double qi0 = 0.0, qi1 = 0.0, qi2 = 0.0, si2 = 0.0;
-        if (has) {
-            int jt;
-            double4 ri;
-            if (ntiles == 1) {  // the cell's own records lie in the staged stencil
-                jt = tj[sh_center + k];
-                ri = trec[sh_center + k];
-            } else {
-                const int pos = d.cell_start[g] + k;
-                jt = d.cell_sites[pos];
-                ri = d.cell_rec[pos];
-            }
-            i = jt >> 2;
-            ti = jt & 3;
-            qi0 = ri.x;
-            qi1 = ri.y;
-            qi2 = ri.z;
-            si2 = ri.w * ri.w;
-        }
-        int n = 0;
-        for (int t = 0; t < ntiles; ++t) {
-            const int t0 = t * kCellTile, t1 = min(T, t0 + kCellTile);
-            if (ntiles > 1) {
-                __syncthreads();  // every wave is done with the previous tile
-                stage(t0, t1);
-                __syncthreads();
-            }
-            if (!has) continue;
-            for (int base = 0; base < t1 - t0; base += kWave) {
-                const int e = base + lane;
-                const bool in = e < t1 - t0;
-                const int jt = tj[in ? e : 0];
-                const double4 rj = trec[in ? e : 0];
-                const int j = jt >> 2;
-                double dx = rj.x - qi0, dy = rj.y - qi1, dz = rj.z - qi2;
-                dx -= pb0 * rint(dx * ib0);
-                dy -= pb1 * rint(dy * ib1);
-                dz -= pb2 * rint(dz * ib2);
-                const float sf = __builtin_sqrtf((float)(si2 + rj.w * rj.w));
-                const double rl = reach + 3.0 * (double)sf;
-                const bool ok = in & (j != i) & (pair_cls(ti, jt & 3) >= 0) &
-                                (dx * dx + dy * dy + dz * dz < rl * rl);
-                const unsigned long long mask = __ballot(ok);
-                const int pos = n + __popcll(mask & __lanemask_lt());
-                if (ok && pos < K2) row[pos] = j;
-                n += __popcll(mask);
-            }
-        }
-        if (has) {
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            if (n > K) over = true;
-            const int nk = min(n, K);
-            int v[E];
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const int t = r * kWave + lane;
-                v[r] = t < min(n, K2) ? row[t] : 0x7fffffff;
-            }
-            wave_sort<E>(v, lane);
-            int lo = 0;
-            int* out = d.nbr + (int64_t)i * K;
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const int t = r * kWave + lane;
-                if (t < nk) {
-                    out[t] = v[r];
-                    lo += (v[r] < i);
+    // The cells in use (count read from the table) are dealt to the XCDs in
+    // contiguous ranges; the blocks of an XCD stride through their range.
+    const int na = d.acell[0].x;
+    const int per = (na + kXcd - 1) / kXcd;
+    const int x0 = (int)(blockIdx.x % kXcd) * per, x1 = min(na, x0 + per);
+    const int nq = (int)gridDim.x / kXcd;
+    for (int b = x0 + (int)(blockIdx.x / kXcd); b < x1; b += nq) {
+        const int2 ac = d.acell[1 + b];
+        const int s = ac.x, g = ac.y;
+        if (!d.ctl[s].rebuild) continue;
+        const int nsite = d.cell_count[g];
+        if (nsite == 0) continue;  // both skips are uniform over the block
+        const SysDesc& S = d.sys[s];
+        __syncthreads();  // the previous cell's tile and stencil are no longer read
+        if (wave == 0) {
+            const int lc = g - (int)S.cell_off;
+            const int c[3] = {lc / (S.nc[1] * S.nc[2]), (lc / S.nc[2]) % S.nc[1], lc % S.nc[2]};
+            int cnt = 0, start = 0;
+            bool center = false;
+            if (lane < 27) {
+                const int64_t cell = stencil_lane_cell(S, c, lane);
+                if (cell >= 0) {
+                    cnt = d.cell_count[cell];
+                    start = d.cell_start[cell];
+                    center = cell == g;
                 }
             }
+            int incl = cnt;  // inclusive wave scan of the counts (lanes >= 27 hold zero)
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) lo += __shfl_xor(lo, o);
-            if (lane == 0) {
-                d.nbr_cnt[i] = nk;
-                d.nbr_lo[i] = lo;
+            for (int o = 1; o < 32; o <<= 1) {
+                const int u = __shfl_up(incl, o);
+                if (lane >= o) incl += u;
             }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            if (lane < 27) {
+                st_start[lane] = start;
+                st_pre[lane] = incl - cnt;
+            }
+            if (lane == 26) st_pre[27] = incl;
+            // the cell itself is one of the stencil cells (the first offset reaching it)
+            const int cl = __ffsll((long long)__ballot(center)) - 1;
+            const int cpre = __shfl(incl - cnt, cl);
+            if (lane == 0) sh_center = cpre;
         }
+        __syncthreads();
+        const int T = st_pre[27];
+        const int ntiles = (T + kCellTile - 1) / kCellTile;
+        const double reach = m.r_c + m.skin + 1e-6;
+        const double ib0 = 1.0 / S.box[0], ib1 = 1.0 / S.box[1], ib2 = 1.0 / S.box[2];
+        // minimum image: periodic axes subtract box * rint(d / box), open axes nothing
+        const double pb0 = S.periodic[0] ? S.box[0] : 0.0, pb1 = S.periodic[1] ? S.box[1] : 0.0,
+                     pb2 = S.periodic[2] ? S.box[2] : 0.0;
+        const int K = d.K;
+        int* row = rows[wave];
+        bool over = false;
+
+        // stage candidates [t0, t1) of the stencil into the tile (whole block); a
+        // thread past t1 loads candidate t0 (always valid) and stores nothing
+        auto stage = [&](int t0, int t1) {
+            constexpr int kPer = kCellTile / kChunk;
+            int pos[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int e = t0 + u * kChunk + (int)threadIdx.x;
+                const int ec = e < t1 ? e : t0;
+                int L = 0;  // stencil cell holding candidate ec: last L with st_pre[L] <= ec
+#pragma unroll
+                for (int step = 16; step > 0; step >>= 1)
+                    if (L + step < 27 && st_pre[L + step] <= ec) L += step;
+                pos[u] = st_start[L] + (ec - st_pre[L]);
+            }
+            int jt[kPer];
+            double4 rj[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                jt[u] = d.cell_sites[pos[u]];
+                rj[u] = d.cell_rec[pos[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int e = u * kChunk + (int)threadIdx.x;
+                if (t0 + e < t1) {
+                    tj[e] = jt[u];
+                    trec[e] = rj[u];
+                }
+            }
+        };
+
+        if (ntiles == 1) {
+            stage(0, T);
+            __syncthreads();
+        }
+        for (int r0 = 0; r0 < nsite; r0 += kWaves) {
+            const int k = r0 + wave;  // this wave's site of the cell in this round
+            const bool has = k < nsite;
+            int i = 0, ti = 0;
+            double qi0 = 0.0, qi1 = 0.0, qi2 = 0.0, si2 = 0.0;
+            if (has) {
+                int jt;
+                double4 ri;
+                if (ntiles == 1) {  // the cell's own records lie in the staged stencil
+                    jt = tj[sh_center + k];
+                    ri = trec[sh_center + k];
+                } else {
+                    const int pos = d.cell_start[g] + k;
+                    jt = d.cell_sites[pos];
+                    ri = d.cell_rec[pos];
+                }
+                i = jt >> 2;
+                ti = jt & 3;
+                qi0 = ri.x;
+                qi1 = ri.y;
+                qi2 = ri.z;
+                si2 = ri.w * ri.w;
+            }
+            int n = 0;
+            for (int t = 0; t < ntiles; ++t) {
+                const int t0 = t * kCellTile, t1 = min(T, t0 + kCellTile);
+                if (ntiles > 1) {
+                    __syncthreads();  // every wave is done with the previous tile
+                    stage(t0, t1);
+                    __syncthreads();
+                }
+                if (!has) continue;
+                for (int base = 0; base < t1 - t0; base += kWave) {
+                    const int e = base + lane;
+                    const bool in = e < t1 - t0;
+                    const int jt = tj[in ? e : 0];
+                    const double4 rj = trec[in ? e : 0];
+                    const int j = jt >> 2;
+                    double dx = rj.x - qi0, dy = rj.y - qi1, dz = rj.z - qi2;
+                    dx -= pb0 * rint(dx * ib0);
+                    dy -= pb1 * rint(dy * ib1);
+                    dz -= pb2 * rint(dz * ib2);
+                    const float sf = __builtin_sqrtf((float)(si2 + rj.w * rj.w));
+                    const double rl = reach + 3.0 * (double)sf;
+                    const bool ok = in & (j != i) & (pair_cls(ti, jt & 3) >= 0) &
+                                    (dx * dx + dy * dy + dz * dz < rl * rl);
+                    const unsigned long long mask = __ballot(ok);
+                    const int pos = n + __popcll(mask & __lanemask_lt());
+                    if (ok && pos < K2) row[pos] = j;
+                    n += __popcll(mask);
+                }
+            }
+            if (has) {
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                if (n > K) over = true;
+                const int nk = min(n, K);
+                int lo = 0;
+                int* out = d.nbr + (int64_t)i * K;
+                if (E > 1 && n <= kWave) {  // a short row: one entry per lane suffices
+                    int v[1] = {lane < n ? row[lane] : 0x7fffffff};
+                    wave_sort<1>(v, lane);
+                    if (lane < nk) {
+                        out[lane] = v[0];
+                        lo += (v[0] < i);
+                    }
+                } else {
+                    int v[E];
+#pragma unroll
+                    for (int r = 0; r < E; ++r) {
+                        const int t = r * kWave + lane;
+                        v[r] = t < min(n, K2) ? row[t] : 0x7fffffff;
+                    }
+                    wave_sort<E>(v, lane);
+#pragma unroll
+                    for (int r = 0; r < E; ++r) {
+                        const int t = r * kWave + lane;
+                        if (t < nk) {
+                            out[t] = v[r];
+                            lo += (v[r] < i);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) lo += __shfl_xor(lo, o);
+                if (lane == 0) {
+                    d.nbr_cnt[i] = nk;
+                    d.nbr_lo[i] = lo;
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            }
+        }
+        if (lane == 0 && over) atomicOr(&d.ctl[s].status, MXE_STAT_KMAX);
     }
-    if (lane == 0 && over) atomicOr(&d.ctl[s].status, MXE_STAT_KMAX);
 }
 
 // Per chunk: the number of pairs its sites own (row entries above the site).
@@ -491,52 +504,52 @@ __global__ __launch_bounds__(kChunk) void k_chunk_up(Dev d) {
     }
 }
 
+// Bonds of a mobile site: same-type sites closer than r_bond. r_bond lies below
+// every list radius, so they are the entries of the site's (sorted) neighbour
+// row that pass the exact FP64 distance test, in row order. kBondLanes lanes
+// per site test consecutive entries; a group ballot keeps them in order.
+constexpr int kBondLanes = 8;
 __global__ __launch_bounds__(kChunk) void k_bonds(Dev d, Model m) {
     const Chunk ch = d.chunks[blockIdx.x];
-    const int i = ch.start + threadIdx.x;
-    if (i >= ch.end) return;
     const int s = ch.sys;
     if (!d.sys[s].force_build) return;  // bonds of the other systems are kept
     const SysDesc& S = d.sys[s];
-    const int B = d.bond_max;
-    const int ti = d.type[i];
-    int n = 0;
+    const int B = d.bond_max, K = d.K;
+    const double rb2 = m.r_bond * m.r_bond;
+    const int grp = threadIdx.x / kBondLanes, sub = threadIdx.x % kBondLanes;
+    const int gshift = (threadIdx.x & 63) & ~(kBondLanes - 1);  // group's first bit in the ballot
     bool over = false;
-    int* out = d.bond + (int64_t)i * B;
-    if (occ_mobile(ti)) {
-        const double rb2 = m.r_bond * m.r_bond;
-        const double qi0 = d.qx[i], qi1 = d.qy[i], qi2 = d.qz[i];
-        const int cc[3] = {cell_coord(qi0, S.box[0], S.cell_w[0], S.nc[0], S.periodic[0]),
-                           cell_coord(qi1, S.box[1], S.cell_w[1], S.nc[1], S.periodic[1]),
-                           cell_coord(qi2, S.box[2], S.cell_w[2], S.nc[2], S.periodic[2])};
-        for (int c = 0; c < 27; ++c) {
-            const int64_t cell = stencil_lane_cell(S, cc, c);
-            if (cell < 0) continue;
-            const int cn = d.cell_count[cell];
-            const int c0 = d.cell_start[cell];
-            for (int e = 0; e < cn; ++e) {
-                const int jt = d.cell_sites[c0 + e];
-                const int j = jt >> 2;
-                if (j == i || (jt & 3) != ti) continue;
-                const double4 rj = d.cell_rec[c0 + e];
-                double dx = rj.x - qi0, dy = rj.y - qi1, dz = rj.z - qi2;
-                min_image(S, dx, dy, dz);
-                if (dx * dx + dy * dy + dz * dz >= rb2) continue;
-                if (n >= B) {
-                    over = true;
-                    continue;
+    for (int i = ch.start + grp; i < ch.end; i += kChunk / kBondLanes) {  // uniform per group
+        const int ti = d.type[i];
+        int n = 0;
+        if (occ_mobile(ti)) {
+            const double qi0 = d.qx[i], qi1 = d.qy[i], qi2 = d.qz[i];
+            const int cnt = d.nbr_cnt[i];
+            const int* row = d.nbr + (int64_t)i * K;
+            int* out = d.bond + (int64_t)i * B;
+            for (int k0 = 0; k0 < cnt; k0 += kBondLanes) {
+                const int k = k0 + sub;
+                int j = 0;
+                bool ok = false;
+                if (k < cnt) {
+                    j = row[k];
+                    if (d.type[j] == ti) {
+                        double dx = d.qx[j] - qi0, dy = d.qy[j] - qi1, dz = d.qz[j] - qi2;
+                        min_image(S, dx, dy, dz);
+                        ok = dx * dx + dy * dy + dz * dz < rb2;
+                    }
                 }
-                int p = n;
-                while (p > 0 && out[p - 1] > j) {
-                    out[p] = out[p - 1];
-                    --p;
+                const unsigned gm = (unsigned)(__ballot(ok) >> gshift) & ((1u << kBondLanes) - 1);
+                const int pos = n + __popc(gm & ((1u << sub) - 1));
+                if (ok) {
+                    if (pos < B) out[pos] = j;
+                    else over = true;
                 }
-                out[p] = j;
-                ++n;
+                n += __popc(gm);
             }
         }
+        if (sub == 0) d.nbond[i] = min(n, B);
     }
-    d.nbond[i] = n;
     if (over) atomicOr(&d.ctl[s].status, MXE_STAT_BONDS);
 }
 
@@ -749,7 +762,7 @@ void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s) {
     k_bin<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_fill<<<d.n_chunks, kChunk, 0, s>>>(d);
-    const int gc = xcd_grid((int)d.n_cells);
+    const int gc = std::min(xcd_grid((int)d.n_cells), kNbrGrid);
     switch (row_pow2(d.K)) {
         case 64: k_nbr<1><<<gc, kChunk, 0, s>>>(d, m); break;
         case 128: k_nbr<2><<<gc, kChunk, 0, s>>>(d, m); break;
