@@ -494,7 +494,7 @@ mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, bool bonds) {
     std::fill(P->dirty.begin(), P->dirty.end(), 0);
     launch_ws_init(d, s);
     launch_sys_init(d, P->model, s);
-    launch_build(d, P->model, bonds, s);
+    launch_build(d, P->model, bonds, true, s);
     HIP_OK(hipGetLastError());
     return MXE_OK;
 }
@@ -535,7 +535,7 @@ void enqueue_eval(mxe_plan* P, const Dev& d, hipStream_t s) {
 }
 
 void enqueue_iteration(mxe_plan* P, const Dev& d, hipStream_t s) {
-    timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, s); });
+    timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, false, s); });
     enqueue_eval(P, d, s);
     timed(P, MXE_K_FIRE, s, [&] {
         launch_control(d, P->model, 1, s);

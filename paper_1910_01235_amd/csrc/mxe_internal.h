@@ -153,6 +153,28 @@ __device__ inline void raise_max(unsigned long long* bits, double v) {
     if (b > *(volatile unsigned long long*)bits) atomicMax(bits, b);
 }
 
+// The lists of a system stay valid while 2 max|dq| + 3 sqrt(2) max(sigma -
+// sigma_build, 0) <= skin (maxima since the last build, recorded by the FIRE
+// update); true when they must be rebuilt.
+__device__ inline bool lists_expired(const SysCtl& c, const Model& m) {
+    const double drift = __longlong_as_double((long long)c.drift_bits);
+    const double widen = __longlong_as_double((long long)c.widen_bits);
+    return 2.0 * sqrt(drift) + 3.0 * sqrt(2.0) * widen > m.skin;
+}
+
+// After a build of system s: count it, clear the request and the maxima,
+// publish the pair count (one thread per system).
+__device__ inline void finish_build(const Dev& d, int s) {
+    SysCtl& c = d.ctl[s];
+    if (!c.rebuild) return;
+    c.n_rebuilds += 1;
+    c.rebuild = 0;
+    c.drift_bits = 0ull;
+    c.widen_bits = 0ull;
+    d.scalars[(int64_t)s * MXE_NSCALARS + MXE_S_PAIRS] = (double)c.n_pairs;
+    d.scalars[(int64_t)s * MXE_NSCALARS + MXE_S_REBUILDS] = (double)c.n_rebuilds;
+}
+
 // is mobile site i (of type t) a reservoir site of the given kind?
 __device__ inline bool held(const Dev& d, int i, int t, int kind) {
     return d.res != nullptr && d.res[i] == kind && occ_mobile(t);
@@ -219,7 +241,9 @@ __device__ inline double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 void launch_ws_init(const Dev& d, hipStream_t s);
 void launch_sys_init(const Dev& d, const Model& m, hipStream_t s);
-void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s);
+// bonds: also rebuild the bond lists; finish: count the build and clear the
+// request at the end of the chain (otherwise the next k_control does it)
+void launch_build(const Dev& d, const Model& m, bool bonds, bool finish, hipStream_t s);
 void launch_relax_init(const Dev& d, const Model& m, hipStream_t s);
 void launch_pair(const Dev& d, const Model& m, int precision, hipStream_t s);
 void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s);

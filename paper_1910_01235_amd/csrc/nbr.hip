@@ -11,8 +11,8 @@
 // largest radius allowed by sigma_cap.
 //
 // Build chain per system (each kernel skips systems whose rebuild flag is 0):
-//   k_build_check  per system: raise the flag when the lists may miss a pair
-//   k_bin        cell of each site and its slot in the cell (atomic count)
+//   k_bin        raises the system's flag when the lists may miss a pair; cell
+//                of each site and its slot in the cell (atomic count)
 //   k_cell_scan  per system: cell offsets (exclusive scan of the counts)
 //   k_fill       place each site in its cell (order within a cell is not
 //                deterministic; rows are sorted afterwards, so nothing depends on it)
@@ -27,7 +27,8 @@
 //                unordered pair is owned by its lower site)
 //   k_pid        per site: pair id of every row entry (binary search in the
 //                sorted row of the other end); pair endpoint arrays
-//   k_build_done per system: clear the flag, count the build
+//   k_build_done per system: clear the flag, count the build (within a
+//                relaxation the following k_control does this instead)
 #include "mxe_internal.h"
 
 namespace mxe {
@@ -170,9 +171,15 @@ __device__ inline int block_excl_scan_1024(int v, int* lds, int& total) {
 
 }  // namespace
 
-__global__ __launch_bounds__(kChunk) void k_bin(Dev d) {
+// Decides whether the system's lists must be rebuilt (every block reads the
+// same maxima and reaches the same decision), then bins the sites.
+__global__ __launch_bounds__(kChunk) void k_bin(Dev d, Model m) {
     const Chunk ch = d.chunks[blockIdx.x];
-    if (!d.ctl[ch.sys].rebuild) return;
+    SysCtl& c = d.ctl[ch.sys];
+    if (!c.rebuild) {
+        if (!lists_expired(c, m)) return;
+        if (threadIdx.x == 0) c.rebuild = 1;  // the same value from every block
+    }
     const int i = ch.start + threadIdx.x;
     if (i >= ch.end) return;
     const SysDesc& S = d.sys[ch.sys];
@@ -729,26 +736,9 @@ __global__ __launch_bounds__(kChunk) void k_pid_remap(Dev d) {
     }
 }
 
-__global__ void k_build_check(Dev d, Model m) {
-    const int s = gtid();
-    if (s >= d.n_sys) return;
-    SysCtl& c = d.ctl[s];
-    const double drift = __longlong_as_double((long long)c.drift_bits);
-    const double widen = __longlong_as_double((long long)c.widen_bits);
-    if (2.0 * sqrt(drift) + 3.0 * sqrt(2.0) * widen > m.skin) c.rebuild = 1;
-}
-
 __global__ void k_build_done(Dev d) {
     const int s = gtid();
-    if (s >= d.n_sys) return;
-    SysCtl& c = d.ctl[s];
-    if (!c.rebuild) return;
-    c.n_rebuilds += 1;
-    c.rebuild = 0;
-    c.drift_bits = 0ull;
-    c.widen_bits = 0ull;
-    d.scalars[(int64_t)s * MXE_NSCALARS + MXE_S_PAIRS] = (double)c.n_pairs;
-    d.scalars[(int64_t)s * MXE_NSCALARS + MXE_S_REBUILDS] = (double)c.n_rebuilds;
+    if (s < d.n_sys) finish_build(d, s);
 }
 
 int row_pow2(int K) {
@@ -757,9 +747,8 @@ int row_pow2(int K) {
     return k2;
 }
 
-void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s) {
-    k_build_check<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d, m);
-    k_bin<<<d.n_chunks, kChunk, 0, s>>>(d);
+void launch_build(const Dev& d, const Model& m, bool bonds, bool finish, hipStream_t s) {
+    k_bin<<<d.n_chunks, kChunk, 0, s>>>(d, m);
     k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_fill<<<d.n_chunks, kChunk, 0, s>>>(d);
     const int gc = std::min(xcd_grid((int)d.n_cells), kNbrGrid);
@@ -775,7 +764,7 @@ void launch_build(const Dev& d, const Model& m, bool bonds, hipStream_t s) {
     k_pid<<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d);
     k_pair_order<<<d.n_pchunks, kChunk, 0, s>>>(d);
     k_pid_remap<<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d);
-    k_build_done<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d);
+    if (finish) k_build_done<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d);
 }
 
 }  // namespace mxe

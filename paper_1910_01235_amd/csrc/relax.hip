@@ -69,6 +69,9 @@ __global__ __launch_bounds__(kChunk) void k_control(Dev d, Model m, int mode) {
     const int s = blockIdx.x;
     SysCtl& c = d.ctl[s];
     if (c.done) return;
+    // a build earlier in this iteration is counted here (the chain's own
+    // finishing kernel is not launched within relaxations)
+    if (threadIdx.x == 0) finish_build(d, s);
     const SysDesc& S = d.sys[s];
     if (S.n_sites == 0) {  // an empty slot evaluates nothing and counts nothing
         if (threadIdx.x == 0) {
