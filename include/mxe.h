@@ -104,7 +104,7 @@ typedef struct {
     double skin;         /* neighbour-list skin (A)                           */
     double r_bond;       /* kinetic-law bond radius: same-type sites closer   */
     int k_max;           /* neighbour-list row length (max neighbours/site), <= 256 */
-    int bond_max;        /* max bonds per site                                */
+    int bond_max;        /* max bonds per site, <= 64                         */
     mxe_precision precision;
     /* launch shapes (performance only; results do not depend on them beyond
      * the order of floating-point sums): lanes per site in the gathers

@@ -184,8 +184,8 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     if (!params || !eam || !systems || n_systems < 1) return fail(MXE_EINVAL, "null argument or n_systems < 1");
     const mxe_params& p = *params;
     if (p.precision != MXE_FP64 && p.precision != MXE_FP32_MIXED) return fail(MXE_EINVAL, "bad precision");
-    if (p.k_max < 1 || p.k_max > 256 || p.bond_max < 1 || p.max_relax < 0)
-        return fail(MXE_EINVAL, "k_max must lie in [1, 256], bond_max >= 1, max_relax >= 0");
+    if (p.k_max < 1 || p.k_max > 256 || p.bond_max < 1 || p.bond_max > 64 || p.max_relax < 0)
+        return fail(MXE_EINVAL, "k_max must lie in [1, 256], bond_max in [1, 64], max_relax >= 0");
     if (p.gather_lanes != 0 && p.gather_lanes != 8 && p.gather_lanes != 16 && p.gather_lanes != 32 &&
         p.gather_lanes != 64)
         return fail(MXE_EINVAL, "gather_lanes must be 0, 8, 16, 32 or 64");

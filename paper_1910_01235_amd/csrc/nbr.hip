@@ -18,9 +18,9 @@
 //                deterministic; rows are sorted afterwards, so nothing depends on it)
 //   k_nbr        one block per cell in use: the stencil's candidates staged in
 //                LDS, one wave per site tests them; survivors are compacted by
-//                ballot and sorted (bitonic, in registers)
+//                ballot and sorted (bitonic, in registers); at the start of a
+//                call also the bonds (same-type sites closer than r_bond, sorted)
 //   k_chunk_up   per chunk: count of "upper" neighbours (larger index)
-//   k_bonds      per mobile site: same-type row entries closer than r_bond (sorted)
 //   k_scan       per system: offsets of the chunks' upper counts; pair count;
 //                clears the cell counts for the next build
 //   k_half       per chunk: offset of each site's first owned pair (each
@@ -281,7 +281,7 @@ __device__ inline void wave_sort(int (&v)[E], int lane) {
     }
 }
 
-constexpr int kCellTile = 768;  // stencil candidates staged in LDS at a time
+constexpr int kCellTile = 704;  // stencil candidates staged in LDS at a time (5 blocks per CU)
 constexpr int kNbrGrid = 16384;  // blocks of the neighbour search at most
 
 // One block per cell in use at a time. Every site of a cell has the same 27-cell stencil,
@@ -296,10 +296,11 @@ constexpr int kNbrGrid = 16384;  // blocks of the neighbour search at most
 // all lie beyond r_c contributes exact zeros). Rows are sorted, so they do not
 // depend on the order of the sites within a cell.
 template <int E>
-__global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
+__global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
     constexpr int K2 = kWave * E;
     constexpr int kWaves = kChunk / kWave;
     __shared__ int rows[kWaves][K2];
+    __shared__ int brows[kWaves][kWave];  // bond partners of each wave's site
     __shared__ int tj[kCellTile];        // 4 * site index + type
     __shared__ double4 trec[kCellTile];  // position and width
     __shared__ int st_start[27], st_pre[28];  // stencil cells: first record, prefix of counts
@@ -318,6 +319,7 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
         const int nsite = d.cell_count[g];
         if (nsite == 0) continue;  // both skips are uniform over the block
         const SysDesc& S = d.sys[s];
+        const bool sys_bonds = bonds != 0 && S.force_build != 0;  // bonds of other systems are kept
         __syncthreads();  // the previous cell's tile and stencil are no longer read
         if (wave == 0) {
             const int lc = g - (int)S.cell_off;
@@ -358,12 +360,12 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
                      pb2 = S.periodic[2] ? S.box[2] : 0.0;
         const int K = d.K;
         int* row = rows[wave];
-        bool over = false;
+        bool over = false, bond_over = false;
 
         // stage candidates [t0, t1) of the stencil into the tile (whole block); a
         // thread past t1 loads candidate t0 (always valid) and stores nothing
         auto stage = [&](int t0, int t1) {
-            constexpr int kPer = kCellTile / kChunk;
+            constexpr int kPer = (kCellTile + kChunk - 1) / kChunk;  // entries per thread
             int pos[kPer];
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
@@ -419,7 +421,11 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
                 qi2 = ri.z;
                 si2 = ri.w * ri.w;
             }
-            int n = 0;
+            // bonds of a mobile site: same-type sites closer than r_bond, by the
+            // exact FP64 distance (minimum image by division)
+            const bool site_bonds = sys_bonds && has && occ_mobile(ti);
+            int* brow = brows[wave];
+            int n = 0, nb = 0;
             for (int t = 0; t < ntiles; ++t) {
                 const int t0 = t * kCellTile, t1 = min(T, t0 + kCellTile);
                 if (ntiles > 1) {
@@ -446,6 +452,16 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
                     const int pos = n + __popcll(mask & __lanemask_lt());
                     if (ok && pos < K2) row[pos] = j;
                     n += __popcll(mask);
+                    if (site_bonds) {  // uniform over the wave
+                        double bx = rj.x - qi0, by = rj.y - qi1, bz = rj.z - qi2;
+                        min_image(S, bx, by, bz);
+                        const bool okb = in & (j != i) & ((jt & 3) == ti) &
+                                         (bx * bx + by * by + bz * bz < m.r_bond * m.r_bond);
+                        const unsigned long long bmask = __ballot(okb);
+                        const int bpos = nb + __popcll(bmask & __lanemask_lt());
+                        if (okb && bpos < kWave) brow[bpos] = j;
+                        nb += __popcll(bmask);
+                    }
                 }
             }
             if (has) {
@@ -485,11 +501,20 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m) {
                     d.nbr_cnt[i] = nk;
                     d.nbr_lo[i] = lo;
                 }
+                if (sys_bonds) {  // uniform over the wave
+                    const int B = d.bond_max, nbk = min(nb, B);
+                    if (nb > B) bond_over = true;
+                    int v[1] = {lane < min(nb, kWave) ? brow[lane] : 0x7fffffff};
+                    wave_sort<1>(v, lane);
+                    if (lane < nbk) d.bond[(int64_t)i * B + lane] = v[0];
+                    if (lane == 0) d.nbond[i] = nbk;
+                }
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             }
         }
         if (lane == 0 && over) atomicOr(&d.ctl[s].status, MXE_STAT_KMAX);
+        if (lane == 0 && bond_over) atomicOr(&d.ctl[s].status, MXE_STAT_BONDS);
     }
 }
 
@@ -509,55 +534,6 @@ __global__ __launch_bounds__(kChunk) void k_chunk_up(Dev d) {
         for (int w = 0; w < kChunk / kWave; ++w) t += lds[w];
         d.chunk_up[blockIdx.x] = t;
     }
-}
-
-// Bonds of a mobile site: same-type sites closer than r_bond. r_bond lies below
-// every list radius, so they are the entries of the site's (sorted) neighbour
-// row that pass the exact FP64 distance test, in row order. kBondLanes lanes
-// per site test consecutive entries; a group ballot keeps them in order.
-constexpr int kBondLanes = 8;
-__global__ __launch_bounds__(kChunk) void k_bonds(Dev d, Model m) {
-    const Chunk ch = d.chunks[blockIdx.x];
-    const int s = ch.sys;
-    if (!d.sys[s].force_build) return;  // bonds of the other systems are kept
-    const SysDesc& S = d.sys[s];
-    const int B = d.bond_max, K = d.K;
-    const double rb2 = m.r_bond * m.r_bond;
-    const int grp = threadIdx.x / kBondLanes, sub = threadIdx.x % kBondLanes;
-    const int gshift = (threadIdx.x & 63) & ~(kBondLanes - 1);  // group's first bit in the ballot
-    bool over = false;
-    for (int i = ch.start + grp; i < ch.end; i += kChunk / kBondLanes) {  // uniform per group
-        const int ti = d.type[i];
-        int n = 0;
-        if (occ_mobile(ti)) {
-            const double qi0 = d.qx[i], qi1 = d.qy[i], qi2 = d.qz[i];
-            const int cnt = d.nbr_cnt[i];
-            const int* row = d.nbr + (int64_t)i * K;
-            int* out = d.bond + (int64_t)i * B;
-            for (int k0 = 0; k0 < cnt; k0 += kBondLanes) {
-                const int k = k0 + sub;
-                int j = 0;
-                bool ok = false;
-                if (k < cnt) {
-                    j = row[k];
-                    if (d.type[j] == ti) {
-                        double dx = d.qx[j] - qi0, dy = d.qy[j] - qi1, dz = d.qz[j] - qi2;
-                        min_image(S, dx, dy, dz);
-                        ok = dx * dx + dy * dy + dz * dz < rb2;
-                    }
-                }
-                const unsigned gm = (unsigned)(__ballot(ok) >> gshift) & ((1u << kBondLanes) - 1);
-                const int pos = n + __popc(gm & ((1u << sub) - 1));
-                if (ok) {
-                    if (pos < B) out[pos] = j;
-                    else over = true;
-                }
-                n += __popc(gm);
-            }
-        }
-        if (sub == 0) d.nbond[i] = min(n, B);
-    }
-    if (over) atomicOr(&d.ctl[s].status, MXE_STAT_BONDS);
 }
 
 // One block per system: offsets of the chunks' owned-pair counts, the pair
@@ -752,13 +728,13 @@ void launch_build(const Dev& d, const Model& m, bool bonds, bool finish, hipStre
     k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_fill<<<d.n_chunks, kChunk, 0, s>>>(d);
     const int gc = std::min(xcd_grid((int)d.n_cells), kNbrGrid);
+    const int nb = bonds ? 1 : 0;
     switch (row_pow2(d.K)) {
-        case 64: k_nbr<1><<<gc, kChunk, 0, s>>>(d, m); break;
-        case 128: k_nbr<2><<<gc, kChunk, 0, s>>>(d, m); break;
-        default: k_nbr<4><<<gc, kChunk, 0, s>>>(d, m); break;
+        case 64: k_nbr<1><<<gc, kChunk, 0, s>>>(d, m, nb); break;
+        case 128: k_nbr<2><<<gc, kChunk, 0, s>>>(d, m, nb); break;
+        default: k_nbr<4><<<gc, kChunk, 0, s>>>(d, m, nb); break;
     }
     k_chunk_up<<<d.n_chunks, kChunk, 0, s>>>(d);
-    if (bonds) k_bonds<<<d.n_chunks, kChunk, 0, s>>>(d, m);
     k_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_half<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_pid<<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d);

@@ -209,6 +209,33 @@ def test_degenerate_lone_sites(mx):
     assert out.fsigma.item() == pytest.approx(o["force"][0, 3], rel=1e-12)
 
 
+def test_run_interstitial_wire_matches_oracle(mx):
+    """Solute hops between the octahedral sites of a host wire (Sec. 3.1 kinetics).
+
+    Two interstitial sites do not interact, so no neighbour row lists such a
+    pair, yet they are bonded (2.56 A apart): the occupancies after the steps
+    check that the bond lists hold interstitial-interstitial bonds."""
+    s = L.jitter(L.nanowire(radius=9.0, n_axial=5, T=700.0), 4, xr=(0.0, 0.9))
+    p = dict(P, max_relax=15, k_max=160, sigma_cap=0.5)  # widths reach 0.31 A on this thin wire
+    say("[gpu] run interstitial wire, 3 steps")
+    plan = mx.Plan([s], EAM, p)
+    st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+    plan.run(st, out, ws, 3, use_graph=True)
+    torch.cuda.synchronize()
+    sc = plan.scalars(out)[0]
+    assert int(sc[mx.S_STATUS]) & mx.FATAL_STATUS == 0
+    r = O.run(EAM, p, s.box, s.periodic, s.T, 3, s.q, s.sigma, s.x, s.type)
+    inter = s.type == L.INTERSTITIAL
+    assert np.abs(r["x"] - s.x)[inter].max() > 1e-4  # the solute does move
+    g = gpu_arrays(plan, st, out)
+    dq = g["q"] - r["q"]
+    dq -= np.array(s.box) * np.round(dq / np.array(s.box)) * np.array(s.periodic)
+    assert np.abs(dq).max() < 1e-10
+    assert rel_err(g["sigma"], r["sigma"], 1e-30) < 1e-10
+    assert rel_err(g["x"], r["x"], 1e-30) < 1e-10
+    assert int(sc[mx.S_UPDATES]) == int(r["updates"][-1])
+
+
 def test_run_multichunk_with_rebuilds(mx):
     """Eight chunks, 20 vacancies at 1000 K: lists are rebuilt inside the relaxations."""
     s = L.vacancy_bulk(8, 20, 1000.0, 1)
