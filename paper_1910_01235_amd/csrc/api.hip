@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "mxe_internal.h"
+#include "taper_poly.h"
 
 using namespace mxe;
 
@@ -245,21 +246,17 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     m.gather_lanes = p.gather_lanes ? p.gather_lanes : 8;
     m.pair_block = p.pair_block ? p.pair_block : 256;
     m.quad_rule = p.quad_rule;
-    // Taylor coefficients 1/k!, highest degree first (signs alternate for sin, cos)
+    // exponential: Taylor coefficients 1/k!, highest degree first; taper: the
+    // near-minimax remainders of taper_poly.h
     {
-        double fact[22];
+        double fact[13];
         fact[0] = 1.0;
-        for (int k = 1; k < 22; ++k) fact[k] = fact[k - 1] * k;
+        for (int k = 1; k < 13; ++k) fact[k] = fact[k - 1] * k;
         for (int k = 0; k < PolyCoef::kExp; ++k) m.poly.ex[k] = 1.0 / fact[12 - k];  // 12 .. 3
-        // sin z / z = 1 - z^2 (1/3! - z^2 (1/5! - ... )): innermost 1/21!, sign alternating
-        for (int k = 0; k < PolyCoef::kSin; ++k) {
-            const int deg = 21 - 2 * k;  // 21, 19, ..., 3
-            m.poly.sn[k] = ((k % 2) ? 1.0 : -1.0) / fact[deg];
-        }
-        for (int k = 0; k < PolyCoef::kCos; ++k) {
-            const int deg = 20 - 2 * k;  // 20, 18, ..., 4
-            m.poly.cs[k] = ((deg / 2) % 2 ? -1.0 : 1.0) / fact[deg];
-        }
+        static_assert(sizeof(kTaperS) == sizeof(m.poly.sn) && sizeof(kTaperC) == sizeof(m.poly.cs),
+                      "taper polynomial degrees");
+        std::memcpy(m.poly.sn, kTaperS, sizeof(kTaperS));
+        std::memcpy(m.poly.cs, kTaperC, sizeof(kTaperC));
     }
 
     // largest list radius the cells must cover

@@ -66,15 +66,16 @@ struct Chunk {
     int pad;
 };
 
-// Polynomial coefficients of the FP64 node arithmetic (Taylor series of e^r
-// to degree 12, of sin z to degree 21 and cos z to degree 20, highest
-// degree first). They travel in the kernel arguments so that the kernels read
-// them into scalar registers.
+// Polynomial coefficients of the FP64 node arithmetic, highest degree first:
+// the Taylor series of e^r to degree 12, and near-minimax remainders of the
+// taper's sine and cosine on |z| <= pi/2 (in w = z^2, from taper_poly.h). They
+// travel in the kernel arguments so that the kernels read them into scalar
+// registers.
 struct PolyCoef {
-    static constexpr int kExp = 10, kSin = 10, kCos = 9;
+    static constexpr int kExp = 10, kSin = 8, kCos = 7;
     double ex[kExp];  // 1/12!, ..., 1/3! (the terms 1/2!, 1, 1 are inline constants)
-    double sn[kSin];  // -1/21!, 1/19!, ..., -1/5!, 1/3!  (sin z = z (1 - z^2 (1/3! - ...)))
-    double cs[kCos];  // 1/20!, -1/18!, ..., 1/4! (the terms -1/2!, 1 are inline constants)
+    double sn[kSin];  // S(w): sin z = z (1 - w S(w)), S(0) = 1/3!
+    double cs[kCos];  // C(w): cos z = 1 + w (-1/2 + w C(w)), C(0) = 1/4!
 };
 
 // Analytic EAM and run parameters, passed by value to the kernels.
