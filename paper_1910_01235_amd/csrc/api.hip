@@ -7,7 +7,7 @@
 #include <vector>
 
 #include "mxe_internal.h"
-#include "taper_poly.h"
+#include "node_poly.h"
 
 using namespace mxe;
 
@@ -246,18 +246,13 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     m.gather_lanes = p.gather_lanes ? p.gather_lanes : 8;
     m.pair_block = p.pair_block ? p.pair_block : 256;
     m.quad_rule = p.quad_rule;
-    // exponential: Taylor coefficients 1/k!, highest degree first; taper: the
-    // near-minimax remainders of taper_poly.h
-    {
-        double fact[13];
-        fact[0] = 1.0;
-        for (int k = 1; k < 13; ++k) fact[k] = fact[k - 1] * k;
-        for (int k = 0; k < PolyCoef::kExp; ++k) m.poly.ex[k] = 1.0 / fact[12 - k];  // 12 .. 3
-        static_assert(sizeof(kTaperS) == sizeof(m.poly.sn) && sizeof(kTaperC) == sizeof(m.poly.cs),
-                      "taper polynomial degrees");
-        std::memcpy(m.poly.sn, kTaperS, sizeof(kTaperS));
-        std::memcpy(m.poly.cs, kTaperC, sizeof(kTaperC));
-    }
+    // near-minimax remainder polynomials of node_poly.h
+    static_assert(sizeof(kExpE) == sizeof(m.poly.ex) && sizeof(kTaperS) == sizeof(m.poly.sn) &&
+                      sizeof(kTaperC) == sizeof(m.poly.cs),
+                  "node polynomial degrees");
+    std::memcpy(m.poly.ex, kExpE, sizeof(kExpE));
+    std::memcpy(m.poly.sn, kTaperS, sizeof(kTaperS));
+    std::memcpy(m.poly.cs, kTaperC, sizeof(kTaperC));
 
     // largest list radius the cells must cover
     P->r_cap = eam->r_c + 3.0 * std::sqrt(2.0) * p.sigma_cap + p.skin;

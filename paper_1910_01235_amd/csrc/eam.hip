@@ -35,8 +35,9 @@ namespace {
 // lie in (0, r_c), so exp sees arguments of modest size and the taper argument
 // lies in [0, 1]. The FP64 routines below exploit that (no special cases):
 //  * exp: Cody-Waite reduction x = n ln2 + r, |r| <= ln2/2 (ln2 split in a
-//    32-bit head and a tail so n * head is exact), e^r by its Taylor series to
-//    degree 12 (truncation < 2.3e-16 relative), then scaling by 2^n.
+//    32-bit head and a tail so n * head is exact), e^r = 1 + r (1 + r (1/2 +
+//    r E(r))) with near-minimax E of degree 8 (relative error below 4e-17),
+//    then scaling by 2^n.
 //  * 1/sqrt: the hardware reciprocal square root refined by one second-order
 //    step (the series of (1 - e)^(-1/2) to e^2).
 //  * taper: with v = t - 1/2 and z = pi v (|z| <= pi/2), cos(pi t) = -sin z and

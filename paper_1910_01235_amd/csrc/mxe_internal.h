@@ -67,13 +67,12 @@ struct Chunk {
 };
 
 // Polynomial coefficients of the FP64 node arithmetic, highest degree first:
-// the Taylor series of e^r to degree 12, and near-minimax remainders of the
-// taper's sine and cosine on |z| <= pi/2 (in w = z^2, from taper_poly.h). They
-// travel in the kernel arguments so that the kernels read them into scalar
-// registers.
+// near-minimax remainders of e^r on |r| <= ln2/2 and of the taper's sine and
+// cosine on |z| <= pi/2 (in w = z^2), from node_poly.h. They travel in the
+// kernel arguments so that the kernels read them into scalar registers.
 struct PolyCoef {
-    static constexpr int kExp = 10, kSin = 8, kCos = 7;
-    double ex[kExp];  // 1/12!, ..., 1/3! (the terms 1/2!, 1, 1 are inline constants)
+    static constexpr int kExp = 9, kSin = 8, kCos = 7;
+    double ex[kExp];  // E(r): e^r = 1 + r (1 + r (1/2 + r E(r))), E(0) = 1/3!
     double sn[kSin];  // S(w): sin z = z (1 - w S(w)), S(0) = 1/3!
     double cs[kCos];  // C(w): cos z = 1 + w (-1/2 + w C(w)), C(0) = 1/4!
 };
