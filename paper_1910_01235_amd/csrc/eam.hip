@@ -295,44 +295,121 @@ struct alignas(16) Vec16 {
     T v[n];
 };
 
+// The 16 moments of one pair from its mean separation (before the minimum
+// image), its two widths and its class.
+template <typename T, int kRule>
+__device__ inline void pair_all_moments(const Model& m, const SysDesc& S, double rx, double ry,
+                                        double rz, double si, double sj, int cls, T out[kFBlk]) {
+#pragma unroll
+    for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
+    min_image(S, rx, ry, rz);
+    const double s = sqrt(si * si + sj * sj);
+    // a pair contributes iff some node lies inside r_c: the farthest node is
+    // 3 s from rbar under the product rule, sqrt(6) max(sigma) under degree 3
+    const double reach = kRule == MXE_QUAD_DEGREE3 ? 2.449489742783178 * fmax(si, sj) : 3.0 * s;
+    if (cls >= 0 && rx * rx + ry * ry + rz * rz < (m.r_c + reach) * (m.r_c + reach)) {
+        if (kRule == MXE_QUAD_DEGREE3) pair_moments_d3<T>(m, cls, rx, ry, rz, si, sj, out);
+        else pair_moments_gh27<T>(m, cls, rx, ry, rz, s, out);
+    }
+}
+
 template <typename T, int kBS, int kRule>
 __global__ __launch_bounds__(kBS, 3) void k_pair(Dev d, Model m) {
+    // Two latency measures, used where they measured faster (the FP64 kernels
+    // and the degree-3 rule; the FP32 27-node kernel, already at high
+    // occupancy, keeps the plain loop and stores):
+    //  * a software pipeline of the pair data: the endpoint indices are loaded
+    //    two pairs ahead and the endpoints' positions, widths and types one
+    //    pair ahead, so the quadrature of a pair never waits for the dependent
+    //    loads of its own data;
+    //  * a thread's 16 moments are staged in LDS and the block writes its kBS
+    //    consecutive force blocks as one contiguous range, 16 B per lane and
+    //    store, so a store covers whole cache lines instead of 16 B of 64 lines.
+    constexpr bool kPipe = sizeof(T) == sizeof(double) || kRule == MXE_QUAD_DEGREE3;
+    constexpr int per = kFBlk / Vec16<T>::n;  // vectors per force block
+    constexpr int kRow = per + 1;             // LDS row (odd stride against bank conflicts)
     // pair chunks are sized to capacity and only the leading ones are active,
     // so they keep the plain order (contiguous ranges per XCD would idle XCDs)
     const Chunk ch = d.pchunks[blockIdx.x];
     const SysCtl& c = d.ctl[ch.sys];
-    if (c.done) return;
+    if (c.done) return;  // uniform over the block
     const SysDesc& S = d.sys[ch.sys];
     const int64_t pend = min((int64_t)ch.end, S.pair_base + min((int64_t)c.n_pairs, S.pair_cap));
     Vec16<T>* fblk = (Vec16<T>*)d.fblk;
-    constexpr int per = kFBlk / Vec16<T>::n;  // vectors per force block
     T* dblk = (T*)d.dblk;
-    for (int64_t p = ch.start + threadIdx.x; p < pend; p += blockDim.x) {
-        const int i = d.pair_i[p], j = d.pair_j[p];
-        double rx = d.qx[j] - d.qx[i], ry = d.qy[j] - d.qy[i], rz = d.qz[j] - d.qz[i];
-        min_image(S, rx, ry, rz);
-        const double si = d.sigma[i], sj = d.sigma[j];
-        const double s = sqrt(si * si + sj * sj);
-        const int cls = pair_cls(d.type[i], d.type[j]);
-        T out[kFBlk];
+
+    if constexpr (!kPipe) {
+        for (int64_t p = ch.start + threadIdx.x; p < pend; p += blockDim.x) {
+            const int i = d.pair_i[p], j = d.pair_j[p];
+            double rx = d.qx[j] - d.qx[i], ry = d.qy[j] - d.qy[i], rz = d.qz[j] - d.qz[i];
+            min_image(S, rx, ry, rz);
+            const double si = d.sigma[i], sj = d.sigma[j];
+            const double s = sqrt(si * si + sj * sj);
+            const int cls = pair_cls(d.type[i], d.type[j]);
+            T out[kFBlk];
 #pragma unroll
-        for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
-        // a pair contributes iff some node lies inside r_c: the farthest node is
-        // 3 s from rbar under the product rule, sqrt(6) max(sigma) under degree 3
-        const double reach = kRule == MXE_QUAD_DEGREE3 ? 2.449489742783178 * fmax(si, sj) : 3.0 * s;
-        if (cls >= 0 && rx * rx + ry * ry + rz * rz < (m.r_c + reach) * (m.r_c + reach)) {
-            if (kRule == MXE_QUAD_DEGREE3) pair_moments_d3<T>(m, cls, rx, ry, rz, si, sj, out);
-            else pair_moments_gh27<T>(m, cls, rx, ry, rz, s, out);
+            for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
+            if (cls >= 0 && rx * rx + ry * ry + rz * rz < (m.r_c + 3.0 * s) * (m.r_c + 3.0 * s))
+                pair_moments_gh27<T>(m, cls, rx, ry, rz, s, out);  // only the 27-node rule comes here
+#pragma unroll
+            for (int v = 0; v < per; ++v) {
+                Vec16<T> b;
+#pragma unroll
+                for (int e = 0; e < Vec16<T>::n; ++e) b.v[e] = out[v * Vec16<T>::n + e];
+                fblk[p * per + v] = b;
+            }
+            dblk[2 * p] = out[M_F];
+            dblk[2 * p + 1] = out[M_F0];
         }
+    } else {
+        // pipelined loop; a pair past the chunk end reads site 0 (always present)
+        // and computes nothing
+        __shared__ Vec16<T> stage[kBS * kRow];
+        auto ends = [&](int64_t q, int& a, int& b) {
+            a = 0;
+            b = 0;
+            if (q < pend) {
+                a = d.pair_i[q];
+                b = d.pair_j[q];
+            }
+        };
+        struct Ends {
+            double xi, yi, zi, si, xj, yj, zj, sj;
+            int ti, tj;
+        };
+        auto site_data = [&](int a, int b) {
+            return Ends{d.qx[a], d.qy[a], d.qz[a], d.sigma[a], d.qx[b], d.qy[b], d.qz[b], d.sigma[b],
+                        (int)d.type[a], (int)d.type[b]};
+        };
+        const int64_t p0 = ch.start + threadIdx.x;
+        int ia, ja;
+        ends(p0, ia, ja);
+        Ends cur = site_data(ia, ja);
+        ends(p0 + kBS, ia, ja);  // indices of the next pair
+        for (int64_t base = ch.start; base < pend; base += kBS) {  // uniform over the block
+            const int64_t p = base + threadIdx.x;
+            const Ends nxt = site_data(ia, ja);  // next pair's data (its indices arrived earlier)
+            ends(p + 2 * kBS, ia, ja);           // indices two pairs ahead
+            T out[kFBlk];
+            pair_all_moments<T, kRule>(m, S, cur.xj - cur.xi, cur.yj - cur.yi, cur.zj - cur.zi, cur.si, cur.sj,
+                                       p < pend ? pair_cls(cur.ti, cur.tj) : -1, out);
+            if (p < pend) {
+                dblk[2 * p] = out[M_F];
+                dblk[2 * p + 1] = out[M_F0];
+            }
 #pragma unroll
-        for (int v = 0; v < per; ++v) {
-            Vec16<T> b;
+            for (int v = 0; v < per; ++v) {
+                Vec16<T> b;
 #pragma unroll
-            for (int e = 0; e < Vec16<T>::n; ++e) b.v[e] = out[v * Vec16<T>::n + e];
-            fblk[p * per + v] = b;
+                for (int e = 0; e < Vec16<T>::n; ++e) b.v[e] = out[v * Vec16<T>::n + e];
+                stage[threadIdx.x * kRow + v] = b;
+            }
+            __syncthreads();
+            const int nb = (int)min((int64_t)kBS, pend - base);  // pairs of this batch
+            for (int q = threadIdx.x; q < nb * per; q += kBS) fblk[base * per + q] = stage[(q / per) * kRow + q % per];
+            __syncthreads();  // the stage is rewritten by the next batch
+            cur = nxt;
         }
-        dblk[2 * p] = out[M_F];
-        dblk[2 * p + 1] = out[M_F0];
     }
 }
 
