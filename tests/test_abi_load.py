@@ -54,6 +54,12 @@ def test_plan_validation_needs_no_gpu():
     with pytest.raises(mxe.MxeError, match="symmetric"):
         bad = dict(w.eam, pair_a=[[0.3, 0.1, 0.2], [0.2, 0.36, 0.2], [0.2, 0.2, 0.0]])
         mxe.Plan(w.systems, bad, w.params)
+    # row and bond lengths are bounded (rows sort in registers, bond rows sit in LDS)
+    with pytest.raises(mxe.MxeError, match="k_max"):
+        mxe.Plan(w.systems, w.eam, dict(w.params, k_max=257))
+    with pytest.raises(mxe.MxeError, match="bond_max"):
+        mxe.Plan(w.systems, w.eam, dict(w.params, bond_max=65))
+    assert mxe.Plan(w.systems, w.eam, dict(w.params, bond_max=64)).n_sites == 256
     # fp32 workspace is smaller (FP32 moments)
     p32 = mxe.Plan(w.systems, w.eam, w.params, precision="fp32")
     assert p32.ws_bytes < plan.ws_bytes
