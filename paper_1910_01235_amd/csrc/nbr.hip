@@ -19,10 +19,10 @@
 //   k_nbr        one block per cell in use: the stencil's candidates staged in
 //                LDS, one wave per site tests them; survivors are compacted by
 //                ballot and sorted (bitonic, in registers); at the start of a
-//                call also the bonds (same-type sites closer than r_bond, sorted)
-//   k_chunk_up   per chunk: count of "upper" neighbours (larger index)
+//                call also the bonds (same-type sites closer than r_bond, sorted);
+//                per-chunk count of "upper" neighbours (larger index)
 //   k_scan       per system: offsets of the chunks' upper counts; pair count;
-//                clears the cell counts for the next build
+//                clears the upper and cell counts for the next build
 //   k_half       per chunk: offset of each site's first owned pair (each
 //                unordered pair is owned by its lower site)
 //   k_pid        per site: pair id of every row entry (binary search in the
@@ -91,6 +91,7 @@ void launch_ws_init(const Dev& d, hipStream_t s) {
     k_fill_site_sys<<<g, 256, 0, s>>>(d);
     const int gc = (int)std::min<int64_t>(4096, (d.n_cells + 255) / 256);
     k_zero_int<<<gc, 256, 0, s>>>(d.cell_count, d.n_cells);
+    k_zero_int<<<(d.n_chunks + 255) / 256, 256, 0, s>>>(d.chunk_up, d.n_chunks);
 }
 
 __global__ void k_sys_init(Dev d) {
@@ -500,6 +501,8 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
                 if (lane == 0) {
                     d.nbr_cnt[i] = nk;
                     d.nbr_lo[i] = lo;
+                    // owned pairs per site chunk (an integer sum: order-independent)
+                    atomicAdd(&d.chunk_up[S.chunk_first + (i - (int)S.site_off) / kChunk], nk - lo);
                 }
                 if (sys_bonds) {  // uniform over the wave
                     const int B = d.bond_max, nbk = min(nb, B);
@@ -518,26 +521,6 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
     }
 }
 
-// Per chunk: the number of pairs its sites own (row entries above the site).
-__global__ __launch_bounds__(kChunk) void k_chunk_up(Dev d) {
-    __shared__ int lds[kChunk / kWave];
-    const Chunk ch = d.chunks[blockIdx.x];
-    if (!d.ctl[ch.sys].rebuild) return;
-    const int i = ch.start + threadIdx.x;
-    int u = i < ch.end ? d.nbr_cnt[i] - d.nbr_lo[i] : 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = u;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kChunk / kWave; ++w) t += lds[w];
-        d.chunk_up[blockIdx.x] = t;
-    }
-}
-
-// One block per system: offsets of the chunks' owned-pair counts, the pair
-// count, and cleared cell counts for the next build.
 __global__ __launch_bounds__(1024) void k_scan(Dev d) {
     __shared__ int lds[1024];
     const int s = blockIdx.x;
@@ -553,6 +536,7 @@ __global__ __launch_bounds__(1024) void k_scan(Dev d) {
     for (int c = a; c < b; ++c) {
         d.chunk_off[S.chunk_first + c] = run;
         run += d.chunk_up[S.chunk_first + c];
+        d.chunk_up[S.chunk_first + c] = 0;  // the next build counts afresh
     }
     if (threadIdx.x == 0) {
         d.ctl[s].n_pairs = total;
@@ -734,7 +718,6 @@ void launch_build(const Dev& d, const Model& m, bool bonds, bool finish, hipStre
         case 128: k_nbr<2><<<gc, kChunk, 0, s>>>(d, m, nb); break;
         default: k_nbr<4><<<gc, kChunk, 0, s>>>(d, m, nb); break;
     }
-    k_chunk_up<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_half<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_pid<<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d);
