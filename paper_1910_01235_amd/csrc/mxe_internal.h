@@ -219,17 +219,6 @@ __device__ inline int xcd_chunk(int n) {
 __host__ __device__ inline int xcd_grid(int n) { return (n + kXcd - 1) / kXcd * kXcd; }
 __device__ inline int gstride() { return gridDim.x * blockDim.x; }
 
-// binary search for the system that owns global index `idx` given an
-// ascending offset field (site_off or cell_off)
-__device__ inline int find_sys_cell(const SysDesc* sys, int n_sys, int64_t idx) {
-    int lo = 0, hi = n_sys - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sys[mid].cell_off <= idx) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);

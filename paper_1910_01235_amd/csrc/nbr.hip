@@ -49,23 +49,6 @@ __device__ inline void min_image(const SysDesc& S, double& dx, double& dy, doubl
     if (S.periodic[2]) dz -= S.box[2] * rint(dz / S.box[2]);
 }
 
-// distinct cell indices of the 3-wide stencil along one axis
-__device__ inline int stencil_axis(int c, int nc, bool periodic, int out[3]) {
-    int n = 0;
-    for (int o = -1; o <= 1; ++o) {
-        int v = c + o;
-        if (periodic) {
-            v = (v + nc) % nc;
-        } else if (v < 0 || v >= nc) {
-            continue;
-        }
-        bool dup = false;
-        for (int k = 0; k < n; ++k) dup |= (out[k] == v);
-        if (!dup) out[n++] = v;
-    }
-    return n;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
