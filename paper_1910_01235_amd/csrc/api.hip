@@ -62,8 +62,14 @@ struct mxe_plan {
     std::vector<const void*> graph_key;
     // profiling: event pairs bracketing launches, per kernel family
     bool prof_on = false;
-    std::vector<hipEvent_t> prof_events;       // pool, reused after each read
-    std::vector<std::pair<int, size_t>> prof_marks;  // (family, index of start event)
+    struct ProfMark {
+        int family;
+        size_t start, end;  // indices into prof_events
+    };
+    std::vector<hipEvent_t> prof_events;  // pool, reused after each read
+    size_t prof_next = 0;                 // next unused event of the pool
+    long prof_last = -1;                  // end event a chained family may start from, or -1
+    std::vector<ProfMark> prof_marks;
     hipError_t prof_err = hipSuccess;
 };
 
@@ -468,6 +474,7 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
 // they changed or the workspace differs, the chunk tables; then initialises
 // the call and builds the lists of every system that must be rebuilt.
 mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, bool bonds) {
+    P->prof_last = -1;  // the untimed launches below break the profiling chain
     // a workspace the plan has not used before holds no lists: build everything
     const bool new_ws = P->tables_ws != (void*)d.sys;
     for (int k = 0; k < P->n_sys; ++k)
@@ -491,58 +498,70 @@ mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, bool bonds) {
     return MXE_OK;
 }
 
-// Runs `launch` on stream s; with profiling on, brackets it with two events.
+// Records the next event of the pool on stream s; returns its index or -1.
+long prof_record(mxe_plan* P, hipStream_t s) {
+    if (P->prof_next == P->prof_events.size()) {
+        hipEvent_t e;
+        const hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            P->prof_err = r;
+            return -1;
+        }
+        P->prof_events.push_back(e);
+    }
+    const hipError_t r = hipEventRecord(P->prof_events[P->prof_next], s);
+    if (r != hipSuccess) {
+        P->prof_err = r;
+        return -1;
+    }
+    return (long)P->prof_next++;
+}
+
+// Runs `launch` on stream s; with profiling on, brackets it with events. A
+// chained family starts from the previous family's end event (they directly
+// follow each other on the stream), so consecutive families share one event:
+// every event on the stream is a point where the queue drains, and one per
+// family boundary costs half as many as a pair per family.
 template <typename F>
-void timed(mxe_plan* P, int family, hipStream_t s, F&& launch) {
+void timed(mxe_plan* P, int family, hipStream_t s, F&& launch, bool chain = false) {
     if (!P->prof_on) {
         launch();
         return;
     }
-    const size_t used = P->prof_marks.size() * 2;
-    while (P->prof_events.size() < used + 2) {
-        hipEvent_t e;
-        hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) {
-            P->prof_err = r;
-            launch();
-            return;
-        }
-        P->prof_events.push_back(e);
-    }
-    hipError_t r1 = hipEventRecord(P->prof_events[used], s);
+    const long start = (chain && P->prof_last >= 0) ? P->prof_last : prof_record(P, s);
     launch();
-    hipError_t r2 = hipEventRecord(P->prof_events[used + 1], s);
-    if (r1 != hipSuccess || r2 != hipSuccess) {
-        P->prof_err = r1 != hipSuccess ? r1 : r2;
-        return;
-    }
-    P->prof_marks.push_back({family, used});
+    const long end = start >= 0 ? prof_record(P, s) : -1;
+    P->prof_last = end;
+    if (end >= 0) P->prof_marks.push_back({family, (size_t)start, (size_t)end});
 }
 
+// The pair kernel always gets a start event of its own, so that its time (the
+// roofline's) holds no launch gap before it.
 void enqueue_eval(mxe_plan* P, const Dev& d, hipStream_t s) {
     const int prec = P->p.precision;
     timed(P, MXE_K_PAIR, s, [&] { launch_pair(d, P->model, prec, s); });
-    timed(P, MXE_K_DENSITY, s, [&] { launch_density(d, P->model, prec, s); });
-    timed(P, MXE_K_FORCE, s, [&] { launch_force(d, P->model, prec, s); });
+    timed(P, MXE_K_DENSITY, s, [&] { launch_density(d, P->model, prec, s); }, true);
+    timed(P, MXE_K_FORCE, s, [&] { launch_force(d, P->model, prec, s); }, true);
 }
 
 void enqueue_iteration(mxe_plan* P, const Dev& d, hipStream_t s) {
-    timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, false, s); });
+    timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, false, s); }, true);
     enqueue_eval(P, d, s);
     timed(P, MXE_K_FIRE, s, [&] {
         launch_control(d, P->model, 1, s);
         launch_update(d, P->model, s);
-    });
+    }, true);
 }
 
 void enqueue_relax(mxe_plan* P, const Dev& d, hipStream_t s) {
     launch_relax_init(d, P->model, s);
+    P->prof_last = -1;  // an untimed launch breaks the chain
     for (int k = 0; k <= P->p.max_relax; ++k) enqueue_iteration(P, d, s);
 }
 
 void enqueue_diffusion_step(mxe_plan* P, const Dev& d, hipStream_t s) {
     enqueue_relax(P, d, s);
-    timed(P, MXE_K_MASTER, s, [&] { launch_master(d, P->model, 0.0, s); });
+    timed(P, MXE_K_MASTER, s, [&] { launch_master(d, P->model, 0.0, s); }, true);
 }
 
 }  // namespace
@@ -559,6 +578,7 @@ extern "C" mxe_status mxe_evaluate(mxe_plan* P, const mxe_state* st, const mxe_o
     launch_relax_init(d, P->model, s);
     enqueue_eval(P, d, s);
     launch_control(d, P->model, 0, s);
+    P->prof_last = -1;
     HIP_OK(hipGetLastError());
     return MXE_OK;
 }
@@ -637,6 +657,7 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
 extern "C" mxe_status mxe_profile(mxe_plan* P, int on) {
     if (!P) return fail(MXE_EINVAL, "null plan");
     P->prof_on = on != 0;
+    P->prof_last = -1;
     return MXE_OK;
 }
 
@@ -650,16 +671,20 @@ extern "C" mxe_status mxe_profile_read(mxe_plan* P, double* ms, int64_t* launche
         const hipError_t e = P->prof_err;
         P->prof_err = hipSuccess;
         P->prof_marks.clear();
+        P->prof_next = 0;
+        P->prof_last = -1;
         return fail(MXE_EDEVICE, std::string("profiling event: ") + hipGetErrorString(e));
     }
     for (const auto& mk : P->prof_marks) {
-        HIP_OK(hipEventSynchronize(P->prof_events[mk.second + 1]));
+        HIP_OK(hipEventSynchronize(P->prof_events[mk.end]));
         float t = 0.0f;
-        HIP_OK(hipEventElapsedTime(&t, P->prof_events[mk.second], P->prof_events[mk.second + 1]));
-        ms[mk.first] += (double)t;
-        launches[mk.first] += 1;
+        HIP_OK(hipEventElapsedTime(&t, P->prof_events[mk.start], P->prof_events[mk.end]));
+        ms[mk.family] += (double)t;
+        launches[mk.family] += 1;
     }
     P->prof_marks.clear();
+    P->prof_next = 0;
+    P->prof_last = -1;
     return MXE_OK;
 }
 
