@@ -172,21 +172,23 @@ __global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
         const double f[4] = {d.fx[i], d.fy[i], d.fz[i], d.fs[i]};
         double* v[4] = {d.vx + i, d.vy + i, d.vz + i, d.vs + i};
         double* y[4] = {d.qx + i, d.qy + i, d.qz + i, d.sigma + i};
+        double yn[4];  // new positions and width, kept in registers (no reloads)
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const double vt = (keep ? *v[a] : 0.0) + dt * f[a];
             const double vn = mv * vt + mf * f[a];
             *v[a] = vn;
-            *y[a] += dt * vn;
+            yn[a] = *y[a] + dt * vn;
         }
-        sg_new = d.sigma[i];
-        if (sg_new < m.sigma_min) {
-            sg_new = m.sigma_min;
-            d.sigma[i] = sg_new;
+        if (yn[3] < m.sigma_min) {
+            yn[3] = m.sigma_min;
             atomicOr(&c.status, MXE_STAT_SIGMA_MIN);
         }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) *y[a] = yn[a];
+        sg_new = yn[3];
         if (sg_new > m.sigma_cap) atomicOr(&c.status, MXE_STAT_SIGMA_CAP);
-        const double dx = d.qx[i] - d.qrx[i], dy = d.qy[i] - d.qry[i], dz = d.qz[i] - d.qrz[i];
+        const double dx = yn[0] - d.qrx[i], dy = yn[1] - d.qry[i], dz = yn[2] - d.qrz[i];
         drift = dx * dx + dy * dy + dz * dz;
         widen = fmax(sg_new - d.sref[i], 0.0);
     }
