@@ -107,9 +107,9 @@ typedef struct {
     int bond_max;        /* max bonds per site, <= 64                         */
     mxe_precision precision;
     /* launch shapes (performance only; results do not depend on them beyond
-     * the order of floating-point sums): lanes per site in the gathers
-     * (0 = 8; 8, 16, 32, 64) and threads per block of the pair kernel
-     * (0 = 256; 64, 128, 256) */
+     * the order of floating-point sums): lanes per site in the density gather
+     * (0 = 8; 8, 16, 32, 64; force_lanes below sets the force gather's) and
+     * threads per block of the pair kernel (0 = 256; 64, 128, 256) */
     int gather_lanes;
     int pair_block;
     /* phase-average rule (App. A): MXE_QUAD_GH27 (default) integrates the
@@ -118,6 +118,9 @@ typedef struct {
      * the pair's 6-D coordinate space (each end displaced by +-sqrt(6) sigma
      * along one axis, weights 1/12) */
     int quad_rule;
+    /* launch shape: lanes per site in the force/mu gather (0 = 16; 8, 16, 32,
+     * 64), performance only as gather_lanes */
+    int force_lanes;
 } mxe_params;
 
 typedef struct {

@@ -1,11 +1,11 @@
 """Launch-shape autotuner for the evaluation kernels.
 
-Two launch shapes change speed but not the method: the lanes per site of the
-density and force gathers (8, 16, 32, 64) and the block size of the pair
-quadrature kernel (64, 128, 256). The tuner times every candidate on the
-workload at hand (HIP events around each kernel launch, through the library's
-profiling switch), keeps the fastest, and caches the choice per size bucket,
-precision and lattice kind in a JSON file.
+Three launch shapes change speed but not the method: the lanes per site of
+the density gather and of the force gather (8, 16, 32, 64 each) and the block
+size of the pair quadrature kernel (64, 128, 256). The tuner times every
+candidate on the workload at hand (HIP events around each kernel launch,
+through the library's profiling switch), keeps the fastest of each, and caches
+the choice per size bucket, precision and lattice kind in a JSON file.
 """
 from __future__ import annotations
 
@@ -71,16 +71,18 @@ def _time_kernels(systems, eam, params, precision, reps, **shape):
 
 def tune(systems, eam: dict, params: dict, precision: str = "fp64", reps: int = 5) -> dict:
     """Time every candidate shape on these systems; return the fastest and the timings."""
-    timings = {"gather_lanes": {}, "pair_block": {}}
-    for g in GATHER_LANES:
-        ms = _time_kernels(systems, eam, params, precision, reps, gather_lanes=g)
-        timings["gather_lanes"][g] = ms["density"] + ms["force"]
+    timings = {"gather_lanes": {}, "force_lanes": {}, "pair_block": {}}
+    for g in GATHER_LANES:  # both gathers at once: each is timed on its own
+        ms = _time_kernels(systems, eam, params, precision, reps, gather_lanes=g, force_lanes=g)
+        timings["gather_lanes"][g] = ms["density"]
+        timings["force_lanes"][g] = ms["force"]
     for b in PAIR_BLOCKS:
         ms = _time_kernels(systems, eam, params, precision, reps, pair_block=b)
         timings["pair_block"][b] = ms["pair"]
     best_g = min(timings["gather_lanes"], key=timings["gather_lanes"].get)
+    best_f = min(timings["force_lanes"], key=timings["force_lanes"].get)
     best_b = min(timings["pair_block"], key=timings["pair_block"].get)
-    return dict(gather_lanes=int(best_g), pair_block=int(best_b),
+    return dict(gather_lanes=int(best_g), force_lanes=int(best_f), pair_block=int(best_b),
                 timings_ms={k: {str(a): round(b, 5) for a, b in v.items()} for k, v in timings.items()})
 
 
@@ -89,8 +91,11 @@ def tuned_params(systems, eam: dict, params: dict, precision: str = "fp64", cach
     """params with the tuned launch shapes (tuned now, or taken from the cache)."""
     key = bucket(systems, precision, int(eam.get("quad_rule", 0)))
     hit = None if (cache is None or retune) else cache.get(key)
+    if hit is not None and "force_lanes" not in hit:
+        hit = None  # written before the force gather had a shape of its own
     if hit is None:
         hit = tune(systems, eam, params, precision, reps)
         if cache is not None:
             cache.put(key, hit)
-    return dict(params, gather_lanes=hit["gather_lanes"], pair_block=hit["pair_block"]), hit
+    return dict(params, gather_lanes=hit["gather_lanes"], force_lanes=hit["force_lanes"],
+                pair_block=hit["pair_block"]), hit

@@ -196,6 +196,9 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     if (p.gather_lanes != 0 && p.gather_lanes != 8 && p.gather_lanes != 16 && p.gather_lanes != 32 &&
         p.gather_lanes != 64)
         return fail(MXE_EINVAL, "gather_lanes must be 0, 8, 16, 32 or 64");
+    if (p.force_lanes != 0 && p.force_lanes != 8 && p.force_lanes != 16 && p.force_lanes != 32 &&
+        p.force_lanes != 64)
+        return fail(MXE_EINVAL, "force_lanes must be 0, 8, 16, 32 or 64");
     if (p.pair_block != 0 && p.pair_block != 64 && p.pair_block != 128 && p.pair_block != 256)
         return fail(MXE_EINVAL, "pair_block must be 0, 64, 128 or 256");
     if (p.quad_rule != MXE_QUAD_GH27 && p.quad_rule != MXE_QUAD_DEGREE3)
@@ -250,6 +253,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     m.nu0 = p.nu0;
     m.Qm = p.Qm;
     m.gather_lanes = p.gather_lanes ? p.gather_lanes : 8;
+    m.force_lanes = p.force_lanes ? p.force_lanes : 16;
     m.pair_block = p.pair_block ? p.pair_block : 256;
     m.quad_rule = p.quad_rule;
     // near-minimax remainder polynomials of node_poly.h

@@ -741,8 +741,8 @@ void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s) 
 }
 
 void launch_force(const Dev& d, const Model& m, int precision, hipStream_t s) {
-    if (precision == MXE_FP32_MIXED) launch_force_t<float>(d, m, m.gather_lanes, s);
-    else launch_force_t<double>(d, m, m.gather_lanes, s);
+    if (precision == MXE_FP32_MIXED) launch_force_t<float>(d, m, m.force_lanes, s);
+    else launch_force_t<double>(d, m, m.force_lanes, s);
 }
 
 }  // namespace mxe

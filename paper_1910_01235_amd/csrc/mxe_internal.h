@@ -86,7 +86,8 @@ struct Model {
     double ftol, dt0, dtmax, alpha0, finc, fdec, falpha;
     int nmin, max_relax;
     double sigma_min, sigma_cap, skin, r_bond, kin_c, dt_safety, nu0, Qm;
-    int gather_lanes, pair_block;  // launch shapes (tuned per workload)
+    int gather_lanes, pair_block;  // launch shapes (tuned per workload): density gather, pair kernel
+    int force_lanes;               // lanes per site of the force gather
     int quad_rule;                 // MXE_QUAD_GH27 or MXE_QUAD_DEGREE3
     PolyCoef poly;
 };

@@ -28,10 +28,12 @@ def test_plan_validates_launch_shapes():
         pytest.skip("libmxe.so not built")
     w = L.config0(0)
     for g in autotune.GATHER_LANES:
-        mxe.Plan(w.systems, w.eam, w.params, gather_lanes=g)
+        mxe.Plan(w.systems, w.eam, w.params, gather_lanes=g, force_lanes=g)
     for b in autotune.PAIR_BLOCKS:
         mxe.Plan(w.systems, w.eam, w.params, pair_block=b)
     with pytest.raises(mxe.MxeError, match="gather_lanes"):
         mxe.Plan(w.systems, w.eam, w.params, gather_lanes=12)
+    with pytest.raises(mxe.MxeError, match="force_lanes"):
+        mxe.Plan(w.systems, w.eam, w.params, force_lanes=24)
     with pytest.raises(mxe.MxeError, match="pair_block"):
         mxe.Plan(w.systems, w.eam, w.params, pair_block=512)

@@ -136,7 +136,8 @@ def test_autotuned_shapes_keep_results(mx, tmp_path):
     ref = None
     for g in autotune.GATHER_LANES:
         for b in (64, 256):
-            plan = mx.Plan([s], L.DEFAULT_EAM, p, gather_lanes=g, pair_block=b)
+            f = autotune.GATHER_LANES[(autotune.GATHER_LANES.index(g) + 1) % len(autotune.GATHER_LANES)]
+            plan = mx.Plan([s], L.DEFAULT_EAM, p, gather_lanes=g, force_lanes=f, pair_block=b)
             st, out, ws = plan.state([s]), plan.out(), plan.workspace()
             plan.evaluate(st, out, ws)
             f = torch.stack([out.fx, out.fy, out.fz, out.fsigma, out.mu], 1).cpu().numpy()
@@ -146,5 +147,6 @@ def test_autotuned_shapes_keep_results(mx, tmp_path):
     cache = autotune.Cache(str(tmp_path / "tune.json"))
     params, hit = autotune.tuned_params([s], L.DEFAULT_EAM, p, "fp64", cache=cache, reps=2)
     assert params["gather_lanes"] in autotune.GATHER_LANES
+    assert params["force_lanes"] in autotune.GATHER_LANES
     assert params["pair_block"] in autotune.PAIR_BLOCKS
     assert cache.get(autotune.bucket([s], "fp64", 0)) == hit
