@@ -329,17 +329,21 @@ __global__ __launch_bounds__(kBS, 3) void k_pair(Dev d, Model m) {
     constexpr int per = kFBlk / Vec16<T>::n;  // vectors per force block
     constexpr int kRow = per + 1;             // LDS row (odd stride against bank conflicts)
     // pair chunks are sized to capacity and only the leading ones are active,
-    // so they keep the plain order (contiguous ranges per XCD would idle XCDs)
-    const Chunk ch = d.pchunks[blockIdx.x];
+    // so they keep the plain order (contiguous ranges per XCD would idle XCDs);
+    // kPairSplit blocks share a chunk, each taking a contiguous sub-range
+    const Chunk ch = d.pchunks[blockIdx.x / kPairSplit];
     const SysCtl& c = d.ctl[ch.sys];
     if (c.done) return;  // uniform over the block
     const SysDesc& S = d.sys[ch.sys];
-    const int64_t pend = min((int64_t)ch.end, S.pair_base + min((int64_t)c.n_pairs, S.pair_cap));
+    constexpr int64_t kSub = kPairChunk / kPairSplit;
+    const int64_t cstart = ch.start + (int64_t)(blockIdx.x % kPairSplit) * kSub;
+    const int64_t pend =
+        min(min((int64_t)ch.end, cstart + kSub), S.pair_base + min((int64_t)c.n_pairs, S.pair_cap));
     Vec16<T>* fblk = (Vec16<T>*)d.fblk;
     T* dblk = (T*)d.dblk;
 
     if constexpr (!kPipe) {
-        for (int64_t p = ch.start + threadIdx.x; p < pend; p += blockDim.x) {
+        for (int64_t p = cstart + threadIdx.x; p < pend; p += blockDim.x) {
             const int i = d.pair_i[p], j = d.pair_j[p];
             double rx = d.qx[j] - d.qx[i], ry = d.qy[j] - d.qy[i], rz = d.qz[j] - d.qz[i];
             min_image(S, rx, ry, rz);
@@ -381,12 +385,12 @@ __global__ __launch_bounds__(kBS, 3) void k_pair(Dev d, Model m) {
             return Ends{d.qx[a], d.qy[a], d.qz[a], d.sigma[a], d.qx[b], d.qy[b], d.qz[b], d.sigma[b],
                         (int)d.type[a], (int)d.type[b]};
         };
-        const int64_t p0 = ch.start + threadIdx.x;
+        const int64_t p0 = cstart + threadIdx.x;
         int ia, ja;
         ends(p0, ia, ja);
         Ends cur = site_data(ia, ja);
         ends(p0 + kBS, ia, ja);  // indices of the next pair
-        for (int64_t base = ch.start; base < pend; base += kBS) {  // uniform over the block
+        for (int64_t base = cstart; base < pend; base += kBS) {  // uniform over the block
             const int64_t p = base + threadIdx.x;
             const Ends nxt = site_data(ia, ja);  // next pair's data (its indices arrived earlier)
             ends(p + 2 * kBS, ia, ja);           // indices two pairs ahead
@@ -698,9 +702,9 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
 template <typename T, int kRule>
 void launch_pair_r(const Dev& d, const Model& m, int bs, hipStream_t s) {
     switch (bs) {
-        case 64: k_pair<T, 64, kRule><<<d.n_pchunks, 64, 0, s>>>(d, m); break;
-        case 128: k_pair<T, 128, kRule><<<d.n_pchunks, 128, 0, s>>>(d, m); break;
-        default: k_pair<T, 256, kRule><<<d.n_pchunks, 256, 0, s>>>(d, m); break;
+        case 64: k_pair<T, 64, kRule><<<d.n_pchunks * kPairSplit, 64, 0, s>>>(d, m); break;
+        case 128: k_pair<T, 128, kRule><<<d.n_pchunks * kPairSplit, 128, 0, s>>>(d, m); break;
+        default: k_pair<T, 256, kRule><<<d.n_pchunks * kPairSplit, 256, 0, s>>>(d, m); break;
     }
 }
 

@@ -12,6 +12,7 @@ constexpr int kFBlk = 16;           // force block per pair: 16 moments = one 12
 constexpr int kSRec = 8;            // per-site record: A~, B~, b, pair amplitude against A, B, S, 2 pad
 constexpr int kChunk = 256;         // sites per site-chunk; block size of per-site kernels
 constexpr int kPairChunk = 4096;    // pair slots per pair-chunk
+constexpr int kPairSplit = 2;       // pair-kernel blocks per pair-chunk (measured: 2 beats 1 and 4)
 constexpr int kNPart = 8;           // partial sums per site-chunk
 constexpr int kWave = 64;
 constexpr double kBoltzmannEv = 8.617333262e-5;  // eV/K
