@@ -134,7 +134,14 @@ __device__ inline void shapes(T r, T inv_re, T al, T ga, T r_s, T tw, T& gp, T& 
     dgf = ef * (dS - ga * inv_re * S);
 }
 
-// 27-node product rule on the relative coordinate (width s)
+// 27-node product rule on the relative coordinate (width s). Node n sits at
+// rbar + h zeta_n with zeta_n in {-1, 0, 1}^3 and h = sqrt(3) s. With
+// c_n = W_n g'(r_n) / r_n for a shape g, the gradient sum_n c_n (rbar + h zeta_n)
+// equals rbar A + h (P - M) and the width sum sqrt(3) sum_n c_n zeta_n . (rbar + h zeta_n)
+// equals sqrt(3) (rbar . (P - M) + h sum_k (P_k + M_k)), where A = sum_n c_n and
+// P_k, M_k sum c_n over the nodes with zeta_k = +1 and -1. So a node only adds
+// c_n to a few sums: to its x plane a (whose three sums give A, P_x and M_x)
+// and to the y and z sums its offset selects.
 template <typename T>
 __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, double ry, double rz,
                                          double s, T out[kFBlk]) {
@@ -143,15 +150,15 @@ __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, dou
     const T r_s = (T)m.r_s, tw = (T)m.taper_inv_w;
     const T rc2 = (T)(m.r_c * m.r_c);
     const T h = (T)s * kSqrt3;
-    const T X[3] = {(T)rx - h, (T)rx, (T)rx + h};
-    const T Y[3] = {(T)ry - h, (T)ry, (T)ry + h};
-    const T Z[3] = {(T)rz - h, (T)rz, (T)rz + h};
-    const T X2[3] = {X[0] * X[0], X[1] * X[1], X[2] * X[2]};
-    const T Y2[3] = {Y[0] * Y[0], Y[1] * Y[1], Y[2] * Y[2]};
-    const T Z2[3] = {Z[0] * Z[0], Z[1] * Z[1], Z[2] * Z[2]};
+    const T R[3] = {(T)rx, (T)ry, (T)rz};
+    const T X2[3] = {(R[0] - h) * (R[0] - h), R[0] * R[0], (R[0] + h) * (R[0] + h)};
+    const T Y2[3] = {(R[1] - h) * (R[1] - h), R[1] * R[1], (R[1] + h) * (R[1] + h)};
+    const T Z2[3] = {(R[2] - h) * (R[2] - h), R[2] * R[2], (R[2] + h) * (R[2] + h)};
     constexpr T w1[3] = {T(1.0 / 6.0), T(2.0 / 3.0), T(1.0 / 6.0)};
 #pragma unroll
     for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
+    // [shape][offset index]: shape 0 = phi, 1 = f; the middle y, z entries stay unused
+    T sx[2][3] = {}, sy[2][3] = {}, sz[2][3] = {};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -165,37 +172,42 @@ __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, dou
                     const T r = r2 * rinv;
                     T gp, dgp, gf, dgf;
                     shapes<T>(r, inv_re, al, ga, r_s, tw, gp, dgp, gf, dgf, m.poly);
-                    // node offset zeta = sqrt(3) (a-1, b-1, c-1); d . zeta
-                    T dz = T(0);
-                    if (a != 1) dz += (a == 2 ? X[a] : -X[a]);
-                    if (b != 1) dz += (b == 2 ? Y[b] : -Y[b]);
-                    if (c != 1) dz += (c == 2 ? Z[c] : -Z[c]);
-                    dz *= kSqrt3;
-                    const T cp = W * dgp * rinv, cf = W * dgf * rinv;
+                    const T wr = W * rinv;
+                    const T cp = wr * dgp, cf = wr * dgf;
                     out[M_PHI] += W * gp;
-                    out[M_GPHI + 0] += cp * X[a];
-                    out[M_GPHI + 1] += cp * Y[b];
-                    out[M_GPHI + 2] += cp * Z[c];
-                    out[M_SPHI] += cp * dz;
                     out[M_F] += W * gf;
-                    out[M_GF + 0] += cf * X[a];
-                    out[M_GF + 1] += cf * Y[b];
-                    out[M_GF + 2] += cf * Z[c];
-                    out[M_SF] += cf * dz;
+                    sx[0][a] += cp;
+                    sx[1][a] += cf;
+                    if (b != 1) {
+                        sy[0][b] += cp;
+                        sy[1][b] += cf;
+                    }
+                    if (c != 1) {
+                        sz[0][c] += cp;
+                        sz[1][c] += cf;
+                    }
                     if (a == 1 && b == 1 && c == 1) {  // node at the mean: rho|_0 terms
                         const T g0 = dgf * rinv;
                         out[M_F0] = gf;
-                        out[M_GF0 + 0] = g0 * X[1];
-                        out[M_GF0 + 1] = g0 * Y[1];
-                        out[M_GF0 + 2] = g0 * Z[1];
+                        out[M_GF0 + 0] = g0 * R[0];
+                        out[M_GF0 + 1] = g0 * R[1];
+                        out[M_GF0 + 2] = g0 * R[2];
                     }
                 }
             }
         }
     }
     const T sinv = T(1) / (T)s;
-    out[M_SPHI] *= sinv;
-    out[M_SF] *= sinv;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int g = q == 0 ? M_GPHI : M_GF, w = q == 0 ? M_SPHI : M_SF;
+        const T A = sx[q][0] + sx[q][1] + sx[q][2];
+        const T B[3] = {sx[q][2] - sx[q][0], sy[q][2] - sy[q][0], sz[q][2] - sz[q][0]};
+        const T C = (sx[q][0] + sx[q][2]) + (sy[q][0] + sy[q][2]) + (sz[q][0] + sz[q][2]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[g + k] = R[k] * A + h * B[k];
+        out[w] = kSqrt3 * (R[0] * B[0] + R[1] * B[1] + R[2] * B[2] + h * C) * sinv;
+    }
     // d/dsigma_e = (sigma_e / s) d/ds: divided by sigma_e both ends get (d/ds)/s
     out[M_SPHI_HI] = out[M_SPHI];
     out[M_SF_HI] = out[M_SF];
@@ -314,7 +326,8 @@ __device__ inline void pair_all_moments(const Model& m, const SysDesc& S, double
 }
 
 template <typename T, int kBS, int kRule>
-__global__ __launch_bounds__(kBS, 3) void k_pair(Dev d, Model m) {
+__global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1)))
+void k_pair(Dev d, Model m) {
     // Two latency measures, used where they measured faster (the FP64 kernels
     // and the degree-3 rule; the FP32 27-node kernel, already at high
     // occupancy, keeps the plain loop and stores):

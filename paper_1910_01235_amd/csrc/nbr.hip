@@ -549,8 +549,13 @@ __global__ __launch_bounds__(kChunk) void k_half(Dev d) {
 
 // One wavefront per site, lanes over its row: the pair id of an entry (i, j)
 // is owned by the lower site; for j < i it is found by binary search of i in
-// j's sorted row (i lies in j's upper part).
-__global__ __launch_bounds__(kChunk) void k_pid(Dev d) {
+// j's sorted row (i lies in j's upper part). The searches are chains of
+// scattered loads and the kernel needs few registers, so a chunk's block has
+// kPidThreads threads to keep more rows in flight (a scan of j's upper part
+// with 16-B loads, one round trip, measured slower: 190 -> 250-307 us).
+constexpr int kPidThreads = 2 * kChunk;
+
+__global__ __launch_bounds__(kPidThreads) void k_pid(Dev d) {
     const int cb = xcd_chunk(d.n_chunks);
     if (cb >= d.n_chunks) return;
     const Chunk ch = d.chunks[cb];
@@ -560,7 +565,7 @@ __global__ __launch_bounds__(kChunk) void k_pid(Dev d) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int K = d.K;
     bool bad = false;
-    for (int i = ch.start + wave; i < ch.end; i += kChunk / kWave) {
+    for (int i = ch.start + wave; i < ch.end; i += kPidThreads / kWave) {
         const int cnt = d.nbr_cnt[i], lo = d.nbr_lo[i], hoff = d.half_off[i];
         const int* row = d.nbr + (int64_t)i * K;
         int* prow = d.pid + (int64_t)i * K;
@@ -608,9 +613,15 @@ __global__ __launch_bounds__(kChunk) void k_pid(Dev d) {
 // to run, but each pair's moments do not depend on its number, and every
 // gather sums over its row in row order, so results are unchanged.
 constexpr int kPairBins = 32 * 24;
+// One kChunk-thread block per pair chunk: a thread takes pairs kOrderThreads
+// apart, so a bucket keeps the pairs of neighbouring sites close together. A
+// 512-thread block renumbers faster (89 -> 79 us on a 256k-site system) but the
+// density gather then reads its pairs with less reuse (170 -> 176 us per
+// evaluation), which costs more than a build saves.
+constexpr int kOrderThreads = kChunk;
 
-__global__ __launch_bounds__(kChunk) void k_pair_order(Dev d) {
-    __shared__ int cnt[kPairBins], start[kPairBins];
+__global__ __launch_bounds__(kOrderThreads) void k_pair_order(Dev d) {
+    __shared__ int cnt[kPairBins], start[kPairBins], wsum[kOrderThreads / kWave];
     const Chunk ch = d.pchunks[blockIdx.x];
     const SysCtl& c = d.ctl[ch.sys];
     if (!c.rebuild) return;
@@ -619,11 +630,11 @@ __global__ __launch_bounds__(kChunk) void k_pair_order(Dev d) {
     if (pend <= ch.start) return;
     for (int b = threadIdx.x; b < kPairBins; b += blockDim.x) cnt[b] = 0;
     __syncthreads();
-    constexpr int kPer = kPairChunk / kChunk;
+    constexpr int kPer = kPairChunk / kOrderThreads;
     int key[kPer], pi[kPer], pj[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-        const int64_t p = ch.start + (int64_t)u * kChunk + threadIdx.x;
+        const int64_t p = ch.start + (int64_t)u * kOrderThreads + threadIdx.x;
         key[u] = -1;
         pi[u] = pj[u] = 0;
         if (p < pend) {
@@ -642,18 +653,39 @@ __global__ __launch_bounds__(kChunk) void k_pair_order(Dev d) {
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int b = 0; b < kPairBins; ++b) {
-            start[b] = run;
-            run += cnt[b];
+    {  // exclusive prefix of the bin counts: kBinsPerT consecutive bins per
+       // thread, a wave scan of the thread totals, then the waves' totals
+        constexpr int kBinsPerT = (kPairBins + kOrderThreads - 1) / kOrderThreads;
+        const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+        int c[kBinsPerT], tot = 0;
+#pragma unroll
+        for (int u = 0; u < kBinsPerT; ++u) {
+            const int b = threadIdx.x * kBinsPerT + u;
+            c[u] = b < kPairBins ? cnt[b] : 0;
+            tot += c[u];
+        }
+        int incl = tot;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        if (lane == kWave - 1) wsum[wave] = incl;
+        __syncthreads();
+        int run = incl - tot;
+        for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+        for (int u = 0; u < kBinsPerT; ++u) {
+            const int b = threadIdx.x * kBinsPerT + u;
+            if (b < kPairBins) start[b] = run;
+            run += c[u];
         }
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         if (key[u] < 0) continue;
-        const int64_t p = ch.start + (int64_t)u * kChunk + threadIdx.x;
+        const int64_t p = ch.start + (int64_t)u * kOrderThreads + threadIdx.x;
         const int64_t t = ch.start + atomicAdd(&start[key[u]], 1);
         d.pair_i[t] = pi[u];
         d.pair_j[t] = pj[u];
@@ -662,14 +694,14 @@ __global__ __launch_bounds__(kChunk) void k_pair_order(Dev d) {
 }
 
 // Rows' pair ids follow the renumbering of k_pair_order.
-__global__ __launch_bounds__(kChunk) void k_pid_remap(Dev d) {
+__global__ __launch_bounds__(kPidThreads) void k_pid_remap(Dev d) {
     const int cb = xcd_chunk(d.n_chunks);
     if (cb >= d.n_chunks) return;
     const Chunk ch = d.chunks[cb];
     if (!d.ctl[ch.sys].rebuild) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int K = d.K;
-    for (int i = ch.start + wave; i < ch.end; i += kChunk / kWave) {
+    for (int i = ch.start + wave; i < ch.end; i += kPidThreads / kWave) {
         const int cnt = d.nbr_cnt[i];
         int* prow = d.pid + (int64_t)i * K;
         for (int k = lane; k < cnt; k += kWave) {
@@ -703,9 +735,9 @@ void launch_build(const Dev& d, const Model& m, bool bonds, bool finish, hipStre
     }
     k_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_half<<<d.n_chunks, kChunk, 0, s>>>(d);
-    k_pid<<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d);
-    k_pair_order<<<d.n_pchunks, kChunk, 0, s>>>(d);
-    k_pid_remap<<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d);
+    k_pid<<<xcd_grid(d.n_chunks), kPidThreads, 0, s>>>(d);
+    k_pair_order<<<d.n_pchunks, kOrderThreads, 0, s>>>(d);
+    k_pid_remap<<<xcd_grid(d.n_chunks), kPidThreads, 0, s>>>(d);
     if (finish) k_build_done<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d);
 }
 
