@@ -260,7 +260,17 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     static_assert(sizeof(kExpE) == sizeof(m.poly.ex) && sizeof(kTaperS) == sizeof(m.poly.sn) &&
                       sizeof(kTaperC) == sizeof(m.poly.cs),
                   "node polynomial degrees");
-    std::memcpy(m.poly.ex, kExpE, sizeof(kExpE));
+    {  // the exponential's remainder in base 2 (argument f = r / ln2)
+        constexpr long double kLn2 = 0.693147180559945309417232121458176568L;
+        for (int k = 0; k < PolyCoef::kExp; ++k) {
+            const int deg = PolyCoef::kExp - 1 - k;  // highest degree first
+            long double sc = kLn2 * kLn2 * kLn2;
+            for (int e = 0; e < deg; ++e) sc *= kLn2;
+            m.poly.ex[k] = (double)((long double)kExpE[k] * sc);
+        }
+        m.poly.ln2 = (double)kLn2;
+        m.poly.ln2sq_half = (double)(kLn2 * kLn2 / 2);
+    }
     std::memcpy(m.poly.sn, kTaperS, sizeof(kTaperS));
     std::memcpy(m.poly.cs, kTaperC, sizeof(kTaperC));
 

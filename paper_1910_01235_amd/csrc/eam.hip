@@ -34,10 +34,13 @@ namespace {
 // Node arithmetic. The arguments are bounded by the pair geometry: distances
 // lie in (0, r_c), so exp sees arguments of modest size and the taper argument
 // lies in [0, 1]. The FP64 routines below exploit that (no special cases):
-//  * exp: Cody-Waite reduction x = n ln2 + r, |r| <= ln2/2 (ln2 split in a
-//    32-bit head and a tail so n * head is exact), e^r = 1 + r (1 + r (1/2 +
-//    r E(r))) with near-minimax E of degree 8 (relative error below 4e-17),
-//    then scaling by 2^n.
+//  * exp: the exponent arrives in base 2, y = x log2(e), formed by one
+//    multiply-add from the distance (the shape constants fold log2(e) in).
+//    y = n + f with n = rint(y) and |f| <= 1/2 exact, and 2^f = e^r with
+//    r = f ln2: 1 + r (1 + r (1/2 + r E(r))) with near-minimax E of degree 8
+//    (relative error below 4e-17), written as a polynomial in f, then
+//    scaling by 2^n. Forming y costs |y| ulp-sized error, as forming the
+//    natural exponent from the distance did before.
 //  * 1/sqrt: the hardware reciprocal square root refined by one second-order
 //    step (the series of (1 - e)^(-1/2) to e^2).
 //  * taper: with v = t - 1/2 and z = pi v (|z| <= pi/2), cos(pi t) = -sin z and
@@ -50,18 +53,15 @@ namespace {
 // the kernels read them with scalar loads and each FMA takes its coefficient
 // as a scalar operand. An FP64 FMA cannot encode a 64-bit literal, so
 // compile-time constants would cost a move into vector registers at every use.
-__device__ inline double exp_bounded(double x, const PolyCoef& c) {
-    constexpr double kLog2e = 1.4426950408889634;
-    constexpr double kLn2Hi = 0.6931471803691238;      // 32 significant bits
-    constexpr double kLn2Lo = 1.9082149292705877e-10;  // ln 2 - kLn2Hi
-    const double n = rint(x * kLog2e);
-    const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, x));
+__device__ inline double exp2_bounded(double y, const PolyCoef& c) {
+    const double n = rint(y);
+    const double f = y - n;  // exact
     double p = c.ex[0];
 #pragma unroll
-    for (int k = 1; k < PolyCoef::kExp; ++k) p = fma(p, r, c.ex[k]);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
+    for (int k = 1; k < PolyCoef::kExp; ++k) p = fma(p, f, c.ex[k]);
+    p = fma(p, f, c.ln2sq_half);
+    p = fma(p, f, c.ln2);
+    p = fma(p, f, 1.0);
     return ldexp(p, (int)n);
 }
 
@@ -76,10 +76,9 @@ __device__ inline double rsqrt_refined(double a) {
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
-// S(t) = (1 + cos(pi t)) / 2 and sin(pi t) for t in [0, 1]
-__device__ inline void taper_terms(double t, double& S, double& sn, const PolyCoef& c) {
-    constexpr double kPi = 3.141592653589793;
-    const double z = kPi * (t - 0.5);
+// S(t) = (1 + cos(pi t)) / 2 and sin(pi t) for t in [0, 1], from
+// z = pi (t - 1/2) in [-pi/2, pi/2]
+__device__ inline void taper_terms(double z, double& S, double& sn, const PolyCoef& c) {
     const double z2 = z * z;
     double ps = c.sn[0];  // sin z = z (1 - w S(w))
 #pragma unroll
@@ -95,43 +94,72 @@ __device__ inline void taper_terms(double t, double& S, double& sn, const PolyCo
     sn = pc;
 }
 
+// Per-pair constants of the two radial shapes g = exp(-a (r/r_e - 1)) S(r)
+// (a = alpha for phi, gamma for f) and of the taper S.
+template <typename T>
+struct ShapeK {
+    T p1, p0, f1, f0;  // base-2 exponents: -a (r/r_e - 1) log2(e) = r x1 + x0
+    T kp, kf;          // a / r_e: minus the slope of each natural exponent
+    T r_s, tw;         // taper start and 1 / taper width
+    T kz, kd;          // pi / width (the taper's z per unit distance), -pi / (2 width)
+};
+
+template <typename T>
+__device__ inline ShapeK<T> shape_consts(const Model& m, int cls) {
+    constexpr double kLog2e = 1.4426950408889634;
+    constexpr double kPi = 3.141592653589793;
+    const double ir = m.inv_re[cls], al = m.alpha[cls], ga = m.gamma[cls], tw = m.taper_inv_w;
+    ShapeK<T> k;
+    k.p1 = (T)(-al * ir * kLog2e);
+    k.p0 = (T)(al * kLog2e);
+    k.f1 = (T)(-ga * ir * kLog2e);
+    k.f0 = (T)(ga * kLog2e);
+    k.kp = (T)(al * ir);
+    k.kf = (T)(ga * ir);
+    k.r_s = (T)m.r_s;
+    k.tw = (T)tw;
+    k.kz = (T)(kPi * tw);
+    k.kd = (T)(-0.5 * kPi * tw);
+    return k;
+}
+
 template <typename T> struct Math;
 
 template <> struct Math<double> {
-    static __device__ inline double ex(double v, const PolyCoef& c) { return exp_bounded(v, c); }
+    static __device__ inline double ex2(double y, const PolyCoef& c) { return exp2_bounded(y, c); }
     static __device__ inline double rsq(double v) { return rsqrt_refined(v); }
-    static __device__ inline void taper(double t, double& S, double& sn, const PolyCoef& c) {
-        taper_terms(t, S, sn, c);
+    // d = r - r_s in [0, width]
+    static __device__ inline void taper(double d, const ShapeK<double>& k, double& S, double& sn,
+                                        const PolyCoef& c) {
+        taper_terms(fma(d, k.kz, -1.5707963267948966), S, sn, c);
     }
 };
 template <> struct Math<float> {
-    static __device__ inline float ex(float v, const PolyCoef&) { return __expf(v); }
+    static __device__ inline float ex2(float y, const PolyCoef&) { return __builtin_amdgcn_exp2f(y); }
     static __device__ inline float rsq(float v) { return __frsqrt_rn(v); }
-    static __device__ inline void taper(float t, float& S, float& sn, const PolyCoef&) {
+    static __device__ inline void taper(float d, const ShapeK<float>& k, float& S, float& sn,
+                                        const PolyCoef&) {
         float c;
-        sincospif(t, &sn, &c);
+        sincospif(d * k.tw, &sn, &c);
         S = 0.5f * (1.0f + c);
     }
 };
 
-// Radial shapes of both pair functions at distance r (r < r_c):
-// g = exp(-a (r/r_e - 1)) S(r), and their derivatives.
+// Both radial shapes and their derivatives at distance r (r < r_c).
 template <typename T>
-__device__ inline void shapes(T r, T inv_re, T al, T ga, T r_s, T tw, T& gp, T& dgp, T& gf, T& dgf,
-                              const PolyCoef& pc) {
-    const T u = r * inv_re - T(1);
-    const T ep = Math<T>::ex(-al * u, pc);
-    const T ef = Math<T>::ex(-ga * u, pc);
+__device__ inline void shapes(T r, const ShapeK<T>& k, T& gp, T& dgp, T& gf, T& dgf, const PolyCoef& pc) {
+    const T ep = Math<T>::ex2(fma(r, k.p1, k.p0), pc);
+    const T ef = Math<T>::ex2(fma(r, k.f1, k.f0), pc);
     T S = T(1), dS = T(0);
-    if (r > r_s) {
+    if (r > k.r_s) {
         T sn;
-        Math<T>::taper((r - r_s) * tw, S, sn, pc);
-        dS = T(-0.5) * T(3.14159265358979323846) * tw * sn;
+        Math<T>::taper(r - k.r_s, k, S, sn, pc);
+        dS = k.kd * sn;
     }
     gp = ep * S;
-    dgp = ep * (dS - al * inv_re * S);
+    dgp = ep * (dS - k.kp * S);
     gf = ef * S;
-    dgf = ef * (dS - ga * inv_re * S);
+    dgf = ef * (dS - k.kf * S);
 }
 
 // 27-node product rule on the relative coordinate (width s). Node n sits at
@@ -146,8 +174,7 @@ template <typename T>
 __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, double ry, double rz,
                                          double s, T out[kFBlk]) {
     constexpr T kSqrt3 = T(1.7320508075688772935);
-    const T inv_re = (T)m.inv_re[cls], al = (T)m.alpha[cls], ga = (T)m.gamma[cls];
-    const T r_s = (T)m.r_s, tw = (T)m.taper_inv_w;
+    const ShapeK<T> K = shape_consts<T>(m, cls);
     const T rc2 = (T)(m.r_c * m.r_c);
     const T h = (T)s * kSqrt3;
     const T R[3] = {(T)rx, (T)ry, (T)rz};
@@ -159,6 +186,10 @@ __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, dou
     for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
     // [shape][offset index]: shape 0 = phi, 1 = f; the middle y, z entries stay unused
     T sx[2][3] = {}, sy[2][3] = {}, sz[2][3] = {};
+    // f and f'/r at the mean separation: the FP64 kernel keeps these two and
+    // forms the gradient after the loop (four live values fewer, no spill);
+    // the FP32 kernel measured faster writing the four terms at the node
+    T f_mid = T(0), g_mid = T(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -171,7 +202,7 @@ __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, dou
                     const T rinv = Math<T>::rsq(r2);
                     const T r = r2 * rinv;
                     T gp, dgp, gf, dgf;
-                    shapes<T>(r, inv_re, al, ga, r_s, tw, gp, dgp, gf, dgf, m.poly);
+                    shapes<T>(r, K, gp, dgp, gf, dgf, m.poly);
                     const T wr = W * rinv;
                     const T cp = wr * dgp, cf = wr * dgf;
                     out[M_PHI] += W * gp;
@@ -187,15 +218,22 @@ __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, dou
                         sz[1][c] += cf;
                     }
                     if (a == 1 && b == 1 && c == 1) {  // node at the mean: rho|_0 terms
-                        const T g0 = dgf * rinv;
-                        out[M_F0] = gf;
-                        out[M_GF0 + 0] = g0 * R[0];
-                        out[M_GF0 + 1] = g0 * R[1];
-                        out[M_GF0 + 2] = g0 * R[2];
+                        f_mid = gf;
+                        g_mid = dgf * rinv;
+                        if constexpr (sizeof(T) != sizeof(double)) {
+                            out[M_F0] = f_mid;
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) out[M_GF0 + k] = g_mid * R[k];
+                        }
                     }
                 }
             }
         }
+    }
+    if constexpr (sizeof(T) == sizeof(double)) {
+        out[M_F0] = f_mid;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[M_GF0 + k] = g_mid * R[k];
     }
     const T sinv = T(1) / (T)s;
 #pragma unroll
@@ -213,18 +251,18 @@ __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, dou
     out[M_SF_HI] = out[M_SF];
 }
 
-// One radial shape and its derivative at r < r_c.
+// The density shape f and its derivative at r < r_c.
 template <typename T>
-__device__ inline void one_shape(T r, T inv_re, T a, T r_s, T tw, T& g, T& dg, const PolyCoef& pc) {
-    const T e = Math<T>::ex(-a * (r * inv_re - T(1)), pc);
+__device__ inline void density_shape(T r, const ShapeK<T>& k, T& g, T& dg, const PolyCoef& pc) {
+    const T e = Math<T>::ex2(fma(r, k.f1, k.f0), pc);
     T S = T(1), dS = T(0);
-    if (r > r_s) {
+    if (r > k.r_s) {
         T sn;
-        Math<T>::taper((r - r_s) * tw, S, sn, pc);
-        dS = T(-0.5) * T(3.14159265358979323846) * tw * sn;
+        Math<T>::taper(r - k.r_s, k, S, sn, pc);
+        dS = k.kd * sn;
     }
     g = e * S;
-    dg = e * (dS - a * inv_re * S);
+    dg = e * (dS - k.kf * S);
 }
 
 // Degree-3 rule of App. A in the pair's six coordinates. A node that moves the
@@ -235,8 +273,7 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
                                        double si, double sj, T out[kFBlk]) {
     constexpr T kSqrt6 = T(2.4494897427831780982);
     constexpr T W = T(1.0 / 12.0);
-    const T inv_re = (T)m.inv_re[cls], al = (T)m.alpha[cls], ga = (T)m.gamma[cls];
-    const T r_s = (T)m.r_s, tw = (T)m.taper_inv_w;
+    const ShapeK<T> K = shape_consts<T>(m, cls);
     const T rc2 = (T)(m.r_c * m.r_c);
     const T R[3] = {(T)rx, (T)ry, (T)rz};
     const T R2[3] = {R[0] * R[0], R[1] * R[1], R[2] * R[2]};
@@ -257,7 +294,7 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
                     const T rinv = Math<T>::rsq(r2);
                     const T r = r2 * rinv;
                     T gp, dgp, gf, dgf;
-                    shapes<T>(r, inv_re, al, ga, r_s, tw, gp, dgp, gf, dgf, m.poly);
+                    shapes<T>(r, K, gp, dgp, gf, dgf, m.poly);
                     const T cp = W * dgp * rinv, cf = W * dgf * rinv;
                     out[M_PHI] += W * gp;
                     out[M_F] += W * gf;
@@ -283,7 +320,7 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
     if (r2c < rc2 && r2c > T(0)) {  // the density at the mean positions
         const T rinv = Math<T>::rsq(r2c);
         T gf, dgf;
-        one_shape<T>(r2c * rinv, inv_re, ga, r_s, tw, gf, dgf, m.poly);
+        density_shape<T>(r2c * rinv, K, gf, dgf, m.poly);
         const T g0 = dgf * rinv;
         out[M_F0] = gf;
         out[M_GF0 + 0] = g0 * R[0];

@@ -73,7 +73,11 @@ struct Chunk {
 // kernel arguments so that the kernels read them into scalar registers.
 struct PolyCoef {
     static constexpr int kExp = 9, kSin = 8, kCos = 7;
-    double ex[kExp];  // E(r): e^r = 1 + r (1 + r (1/2 + r E(r))), E(0) = 1/3!
+    // 2^f = 1 + f (ln2 + f (ln2^2/2 + f E2(f))) with E2(f) = ln2^3 E(f ln2), where
+    // e^r = 1 + r (1 + r (1/2 + r E(r))); ex holds E2 and ln2, ln2sq_half the
+    // two leading coefficients (all rounded from extended precision)
+    double ex[kExp];
+    double ln2, ln2sq_half;
     double sn[kSin];  // S(w): sin z = z (1 - w S(w)), S(0) = 1/3!
     double cs[kCos];  // C(w): cos z = 1 + w (-1/2 + w C(w)), C(0) = 1/4!
 };

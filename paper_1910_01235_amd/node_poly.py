@@ -1,8 +1,9 @@
 """Writes csrc/node_poly.h: near-minimax polynomials of the FP64 node arithmetic.
 
-* Exponential on |r| <= ln2/2 (after Cody-Waite reduction):
+* Exponential on |r| <= ln2/2 (the reduction y = n + f, |f| <= 1/2, r = f ln2):
       e^r = 1 + r (1 + r (1/2 + r E(r))),   E of degree 8,
   relative error of e^r below 4e-17 (Taylor to degree 12 would leave 2.3e-16).
+  The plan scales E to the base-2 form the kernels evaluate.
 * Taper sine and cosine on |z| <= pi/2, in w = z^2:
       sin z = z (1 - w S(w)),   cos z = 1 + w (-1/2 + w C(w)),
   S of degree 7 and C of degree 6, absolute errors about 1e-18 and 6e-17.

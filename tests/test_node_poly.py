@@ -1,9 +1,9 @@
 """The remainder polynomials of the FP64 node arithmetic.
 
 csrc/node_poly.h must be what paper_1910_01235_amd/node_poly.py writes, and the
-polynomials must reproduce e^r on |r| <= ln2/2 (the range left by Cody-Waite
-reduction) and sin z, cos z on |z| <= pi/2 (the taper's range) to FP64
-rounding."""
+polynomials must reproduce e^r on |r| <= ln2/2 (the range left by the
+reduction y = n + f, r = f ln2; also in the base-2 form the kernels evaluate)
+and sin z, cos z on |z| <= pi/2 (the taper's range) to FP64 rounding."""
 import math
 import re
 
@@ -41,6 +41,26 @@ def test_exponential_polynomial():
         ex = mp.exp(mp.mpf(r))
         worst = max(worst, abs(float((mp.mpf(v) - ex) / ex)))
     # a few ulp (Horner without fused multiply-adds in Python)
+    assert worst < 4e-16, worst
+
+
+def test_base_two_form_of_the_exponential():
+    """The kernels evaluate 2^f on |f| <= 1/2 as 1 + f (ln2 + f (ln2^2/2 + f E2(f)))
+    with E2(f) = ln2^3 E(f ln2), the coefficients rounded from higher precision."""
+    E, _, _ = _header()
+    mp.mp.dps = 40
+    ln2 = mp.log(2)
+    deg = len(E) - 1
+    E2 = [float(mp.mpf(c) * ln2 ** (deg - k + 3)) for k, c in enumerate(E)]
+    l1, l2h = float(ln2), float(ln2 * ln2 / 2)
+    worst = 0.0
+    for f in np.concatenate([np.linspace(-0.5, 0.5, 4001), [0.0, 1e-12, -1e-12]]):
+        p = E2[0]
+        for c in E2[1:]:
+            p = p * f + c
+        v = 1.0 + f * (l1 + f * (l2h + f * p))
+        ex = mp.power(2, mp.mpf(f))
+        worst = max(worst, abs(float((mp.mpf(v) - ex) / ex)))
     assert worst < 4e-16, worst
 
 
