@@ -54,7 +54,7 @@ struct mxe_plan {
     size_t o_sys, o_ctl, o_chunks, o_pchunks, o_site_sys, o_cell_count, o_cell_start, o_cell_sites, o_cell_rec;
     size_t o_cell_of, o_slot_of, o_chunk_up, o_chunk_off, o_acell;
     size_t o_nbr, o_cnt, o_lo, o_pid, o_hoff, o_pi, o_pj, o_pnew, o_fblk, o_dblk, o_G, o_A, o_B;
-    size_t o_v, o_qr, o_sref, o_emit, o_srec, o_bond, o_nbond, o_part;
+    size_t o_v, o_qr, o_sref, o_emit, o_srec, o_bond, o_nbond, o_part, o_part_sub;
     size_t ws_bytes = 0;
     // graph cache for mxe_run
     hipStream_t cap_stream = nullptr;
@@ -370,6 +370,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     P->o_bond = take(sizeof(int) * N * p.bond_max);
     P->o_nbond = take(sizeof(int) * N);
     P->o_part = take(sizeof(double) * kNPart * P->chunks.size());
+    P->o_part_sub = take(sizeof(double) * kNPart * kForceSplit * P->chunks.size());
     P->ws_bytes = o;
     *out = P;
     return MXE_OK;
@@ -472,6 +473,7 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.bond = (int*)(w + P->o_bond);
     D.nbond = (int*)(w + P->o_nbond);
     D.part = (double*)(w + P->o_part);
+    D.part_sub = (double*)(w + P->o_part_sub);
     D.n_sites = (int)N;
     D.n_sys = P->n_sys;
     D.n_chunks = (int)P->chunks.size();

@@ -481,14 +481,17 @@ __device__ inline double group_sum(double v) {
 template <typename T, int kLPS>
 __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
     constexpr int kGroups = kChunk / kLPS;
-    const int cb = xcd_chunk(d.n_chunks);
-    if (cb >= d.n_chunks) return;
-    const Chunk ch = d.chunks[cb];
+    // kGatherSplit blocks per site chunk, each taking a contiguous part of it
+    const int ub = xcd_chunk(d.n_chunks * kGatherSplit);
+    if (ub >= d.n_chunks * kGatherSplit) return;
+    const Chunk ch = d.chunks[ub / kGatherSplit];
+    constexpr int kPart = kChunk / kGatherSplit;
+    const int i_lo = ch.start + (ub % kGatherSplit) * kPart, i_hi = min(ch.end, i_lo + kPart);
     if (d.ctl[ch.sys].done) return;
     const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
     const T* dblk = (const T*)d.dblk;
     const int K = d.K;
-    for (int i = ch.start + grp; i < ch.end; i += kGroups) {
+    for (int i = i_lo + grp; i < i_hi; i += kGroups) {
         const int cnt = d.nbr_cnt[i];
         const int* row = d.nbr + (int64_t)i * K;
         const int* prow = d.pid + (int64_t)i * K;
@@ -574,9 +577,14 @@ template <typename T, int kLPS>
 __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
     constexpr int kGroups = kChunk / kLPS;
     __shared__ double red[kGroups][6];
-    const int cb = xcd_chunk(d.n_chunks);
-    if (cb >= d.n_chunks) return;
+    // kForceSplit blocks per site chunk, each taking a contiguous part of it
+    // and writing its own partial row (k_force_fold combines a chunk's rows)
+    const int ub = xcd_chunk(d.n_chunks * kForceSplit);
+    if (ub >= d.n_chunks * kForceSplit) return;
+    const int cb = ub / kForceSplit;
+    constexpr int kPart = kChunk / kForceSplit;
     const Chunk ch = d.chunks[cb];
+    const int i_lo = ch.start + (ub % kForceSplit) * kPart, i_hi = min(ch.end, i_lo + kPart);
     const int sys = ch.sys;
     if (d.ctl[sys].done) return;
     const SysDesc& S = d.sys[sys];
@@ -590,7 +598,7 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
     const int K = d.K;
     double pe = 0.0, pfmax = 0.0, pfv = 0.0, pff = 0.0, pvv = 0.0, psx = 0.0;
     int bad = 0;
-    for (int i = ch.start + grp; i < ch.end; i += kGroups) {
+    for (int i = i_lo + grp; i < i_hi; i += kGroups) {
         const int ti = d.type[i];
         const double xi = d.x[i], si = d.sigma[i];
         const double Ahi = d.Ahat[i], Bhi = d.Bhat[i];
@@ -730,7 +738,6 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double* P = d.part + (int64_t)cb * kNPart;
         double e = red[0][0], fm = red[0][1], fv = red[0][2], ff = red[0][3], vv = red[0][4], sx = red[0][5];
         for (int g = 1; g < kGroups; ++g) {
             e += red[g][0];
@@ -740,12 +747,41 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
             vv += red[g][4];
             sx += red[g][5];
         }
-        P[P_E] = e;
-        P[P_FMAX] = fm;
-        P[P_FV] = fv;
-        P[P_FF] = ff;
-        P[P_VV] = vv;
-        P[P_SUMX] = sx;
+        double* Q = d.part_sub + (int64_t)ub * kNPart;
+        Q[P_E] = e;
+        Q[P_FMAX] = fm;
+        Q[P_FV] = fv;
+        Q[P_FF] = ff;
+        Q[P_VV] = vv;
+        Q[P_SUMX] = sx;
+    }
+}
+
+// A site chunk's kForceSplit partial rows summed into the chunk's row, by
+// kForceSplit lanes per chunk with a fixed butterfly order (deterministic).
+// A separate launch: a fence in every force block would write back the L2.
+__global__ __launch_bounds__(kChunk) void k_force_fold(Dev d) {
+    static_assert(kForceSplit <= kWave && (kForceSplit & (kForceSplit - 1)) == 0, "fold width");
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cb = t / kForceSplit, k = t % kForceSplit;
+    const bool live = cb < d.n_chunks && !d.ctl[d.chunks[cb < d.n_chunks ? cb : 0].sys].done;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (live) {
+        const double2* R = (const double2*)(d.part_sub + ((int64_t)cb * kForceSplit + k) * kNPart);
+        const double2 a = R[0], b = R[1], c = R[2];
+        v[0] = a.x, v[1] = a.y, v[2] = b.x, v[3] = b.y, v[4] = c.x, v[5] = c.y;
+    }
+#pragma unroll
+    for (int o = 1; o < kForceSplit; o <<= 1) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const double w = __shfl_xor(v[j], o);
+            v[j] = j == P_FMAX ? fmax(v[j], w) : v[j] + w;
+        }
+    }
+    if (live && k == 0) {
+        double* P = d.part + (int64_t)cb * kNPart;
+        for (int j = 0; j < 6; ++j) P[j] = v[j];
     }
 }
 
@@ -767,20 +803,20 @@ void launch_pair_t(const Dev& d, const Model& m, int bs, hipStream_t s) {
 template <typename T>
 void launch_density_t(const Dev& d, const Model& m, int lps, hipStream_t s) {
     switch (lps) {
-        case 8: k_density<T, 8><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
-        case 32: k_density<T, 32><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
-        case 64: k_density<T, 64><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
-        default: k_density<T, 16><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        case 8: k_density<T, 8><<<xcd_grid(d.n_chunks * kGatherSplit), kChunk, 0, s>>>(d, m); break;
+        case 32: k_density<T, 32><<<xcd_grid(d.n_chunks * kGatherSplit), kChunk, 0, s>>>(d, m); break;
+        case 64: k_density<T, 64><<<xcd_grid(d.n_chunks * kGatherSplit), kChunk, 0, s>>>(d, m); break;
+        default: k_density<T, 16><<<xcd_grid(d.n_chunks * kGatherSplit), kChunk, 0, s>>>(d, m); break;
     }
 }
 
 template <typename T>
 void launch_force_t(const Dev& d, const Model& m, int lps, hipStream_t s) {
     switch (lps) {
-        case 8: k_force<T, 8><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
-        case 32: k_force<T, 32><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
-        case 64: k_force<T, 64><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
-        default: k_force<T, 16><<<xcd_grid(d.n_chunks), kChunk, 0, s>>>(d, m); break;
+        case 8: k_force<T, 8><<<xcd_grid(d.n_chunks * kForceSplit), kChunk, 0, s>>>(d, m); break;
+        case 32: k_force<T, 32><<<xcd_grid(d.n_chunks * kForceSplit), kChunk, 0, s>>>(d, m); break;
+        case 64: k_force<T, 64><<<xcd_grid(d.n_chunks * kForceSplit), kChunk, 0, s>>>(d, m); break;
+        default: k_force<T, 16><<<xcd_grid(d.n_chunks * kForceSplit), kChunk, 0, s>>>(d, m); break;
     }
 }
 
@@ -797,6 +833,7 @@ void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s) 
 void launch_force(const Dev& d, const Model& m, int precision, hipStream_t s) {
     if (precision == MXE_FP32_MIXED) launch_force_t<float>(d, m, m.force_lanes, s);
     else launch_force_t<double>(d, m, m.force_lanes, s);
+    k_force_fold<<<(d.n_chunks * kForceSplit + kChunk - 1) / kChunk, kChunk, 0, s>>>(d);
 }
 
 }  // namespace mxe

@@ -14,6 +14,8 @@ constexpr int kChunk = 256;         // sites per site-chunk; block size of per-s
 constexpr int kPairChunk = 4096;    // pair slots per pair-chunk
 constexpr int kPairSplit = 2;       // pair-kernel blocks per pair-chunk (measured: 2 beats 1 and 4)
 constexpr int kNPart = 8;           // partial sums per site-chunk
+constexpr int kForceSplit = 8;      // force-gather blocks (and partial rows) per site chunk
+constexpr int kGatherSplit = 8;     // density-gather blocks per site chunk
 constexpr int kWave = 64;
 constexpr double kBoltzmannEv = 8.617333262e-5;  // eV/K
 
@@ -132,6 +134,7 @@ struct Dev {
     double *qrx, *qry, *qrz, *sref;
     int *bond, *nbond;
     double* part;
+    double* part_sub;  // [chunk][kForceSplit][kNPart]: the force gather's block rows
     int n_sites, n_sys, n_chunks, n_pchunks;
     int K, bond_max;
     int64_t n_cells, pair_cap_total;
