@@ -38,6 +38,10 @@ OPS_PER_PAIR = 27 * 90
 # state, embedding terms, FIRE velocity and the six outputs.
 BYTES_FORCE_PER_PAIR = 2 * (14 * 8 + 8)
 BYTES_FORCE_PER_SITE = 8 + 8 + 1 + 8 * 3 + 8 * 4 + 8 * 6
+# The timed runs bracket only the pair kernel with HIP events (every event
+# drains the queue); the per-family breakdown comes from this many further
+# steps with every family bracketed.
+BREAKDOWN_STEPS = 2
 
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
 # this bench (--steps 2 --warmup 1 --no-extras --no-cpu-baseline --calib-copy),
@@ -47,9 +51,9 @@ BYTES_FORCE_PER_SITE = 8 + 8 + 1 + 8 * 3 + 8 * 4 + 8 * 6
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
     sources_sha256_16="7084218a61128e23",
-    pair=dict(fetch_kib=162612.2, write_kib=1013383.7),
-    force=dict(fetch_kib=894302.7, write_kib=13585.4),
-    density=dict(fetch_kib=181209.5, write_kib=32681.2),
+    pair=dict(fetch_kib=159685.8, write_kib=1019787.0),
+    force=dict(fetch_kib=900297.5, write_kib=13651.4),
+    density=dict(fetch_kib=182437.6, write_kib=32815.4),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -152,6 +156,8 @@ def batched_legs(n_requests: int, n_steps: int, seed: int = 4):
 
 
 def timed_run(plan, st, out, ws, steps, use_graph, profile):
+    """profile: False, "pair" (events around the pair kernel only: the timed
+    runs) or True (every kernel family: the breakdown runs)."""
     import torch
     plan.profile(profile)
     if profile:
@@ -204,27 +210,33 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup done: status {int(plan.scalars(out)[0, mxe.S_STATUS])}")
 
-    wall, sc, prof = timed_run(plan, st, out, ws, args.steps, use_graph=False, profile=True)
+    # the timed region brackets only the pair kernel (the roofline's) with events
+    wall, sc, prof = timed_run(plan, st, out, ws, args.steps, use_graph=False, profile="pair")
     evals = int(sc[mxe.S_TOTAL_EVALS])
     pair_evals = float(sc[mxe.S_PAIR_EVALS])
     status = int(sc[mxe.S_STATUS])
     value = n * evals / wall
     site_steps = n_mobile * args.steps / wall
     log(f"timed: {wall:.3f} s, {evals} evaluations, status {status}")
+    pair_ms, pair_launches = prof["pair"]
+    # every family from BREAKDOWN_STEPS more steps with all families bracketed
+    _, sc_b, prof_b = timed_run(plan, st, out, ws, BREAKDOWN_STEPS, use_graph=False, profile=True)
+    evals_b, pair_evals_b = int(sc_b[mxe.S_TOTAL_EVALS]), float(sc_b[mxe.S_PAIR_EVALS])
+    log(f"breakdown: {BREAKDOWN_STEPS} steps, {evals_b} evaluations")
 
     # roofline of each hot kernel family
     fam = {}
-    for k, (ms, cnt) in prof.items():
+    for k, (ms, cnt) in prof_b.items():
         fam[k] = dict(ms_total=ms, launches=cnt, ms_avg=(ms / cnt if cnt else 0.0))
-    pairs_per_launch = pair_evals / max(fam["pair"]["launches"], 1)
+    pairs_per_launch = pair_evals / max(pair_launches, 1)
     ops = OPS_PER_PAIR * pairs_per_launch
-    pair_avg_s = fam["pair"]["ms_avg"] / 1e3
+    pair_avg_s = pair_ms / max(pair_launches, 1) / 1e3
     roof_pair = dict(bound="alu", achieved=ops / pair_avg_s / 1e12 if pair_avg_s > 0 else 0.0,
                      peak=PEAK_FP64_TOPS, unit="Tops/s", kernel="k_pair<double>",
                      traffic=counter_traffic("pair"), traffic_unit="B/launch")
     roof_pair["frac"] = roof_pair["achieved"] / roof_pair["peak"]
-    evals_per_launch = evals / max(fam["force"]["launches"], 1)
-    bytes_force = (BYTES_FORCE_PER_PAIR * pair_evals / max(evals, 1) + BYTES_FORCE_PER_SITE * n) \
+    evals_per_launch = evals_b / max(fam["force"]["launches"], 1)
+    bytes_force = (BYTES_FORCE_PER_PAIR * pair_evals_b / max(evals_b, 1) + BYTES_FORCE_PER_SITE * n) \
         * evals_per_launch
     force_avg_s = fam["force"]["ms_avg"] / 1e3
     roof_force = dict(bound="hbm", achieved=bytes_force / force_avg_s / 1e9 if force_avg_s > 0 else 0.0,
@@ -250,7 +262,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "sites": n, "vacancies": int((s.x == 0).sum()),
                    "T_K": s.T, "quadrature_nodes": 27, "max_relax": w.params["max_relax"],
-                   "precision": "fp64", "launch": "eager with per-kernel HIP events"},
+                   "precision": "fp64", "launch": "eager; HIP events around the pair kernel"},
         "site_steps_per_s": site_steps,
         "evals_in_timed_steps": evals,
         "list_builds_in_timed_steps": int(sc[mxe.S_REBUILDS]),
@@ -258,7 +270,9 @@ def main():
         "status": status,
         "roofline": roofline,
         "roofline_all": {"pair": roof_pair, "force": roof_force},
+        "pair_ms_avg_timed": pair_ms / max(pair_launches, 1),
         "kernel_ms": fam,
+        "kernel_ms_from": f"{BREAKDOWN_STEPS} steps after the timed region, every family bracketed",
         "dominant_kernel": dominant,
     }
 
@@ -273,9 +287,10 @@ def main():
         p32 = mxe.Plan([s], w.eam, w.params, precision="fp32")
         st32, out32, ws32 = p32.state([s]), p32.out(), p32.workspace()
         p32.run(st32, out32, ws32, args.warmup, use_graph=True)
-        wall_32, sc_32, prof32 = timed_run(p32, st32, out32, ws32, args.steps, use_graph=False,
-                                           profile=True)
+        wall_32, sc_32, _ = timed_run(p32, st32, out32, ws32, args.steps, use_graph=False,
+                                      profile="pair")
         ev32 = int(sc_32[mxe.S_TOTAL_EVALS])
+        _, _, prof32 = timed_run(p32, st32, out32, ws32, BREAKDOWN_STEPS, use_graph=False, profile=True)
         result["fp32_mixed"] = dict(value=n * ev32 / wall_32, ms_per_step=wall_32 / args.steps * 1e3,
                                     evals=ev32, status=int(sc_32[mxe.S_STATUS]),
                                     kernel_ms={k: v[0] for k, v in prof32.items()})
@@ -289,8 +304,9 @@ def main():
             p3 = mxe.Plan([s], eam3, w.params, precision=prec)
             st3, out3, ws3 = p3.state([s]), p3.out(), p3.workspace()
             p3.run(st3, out3, ws3, args.warmup, use_graph=True)
-            wall3, sc3, prof3 = timed_run(p3, st3, out3, ws3, args.steps, use_graph=False, profile=True)
+            wall3, sc3, _ = timed_run(p3, st3, out3, ws3, args.steps, use_graph=False, profile="pair")
             ev3 = int(sc3[mxe.S_TOTAL_EVALS])
+            _, _, prof3 = timed_run(p3, st3, out3, ws3, BREAKDOWN_STEPS, use_graph=False, profile=True)
             result["degree3"][prec] = dict(
                 value=n * ev3 / wall3, ms_per_step=wall3 / args.steps * 1e3, evals=ev3,
                 status=int(sc3[mxe.S_STATUS]),
@@ -315,8 +331,9 @@ def main():
                 stv.reservoir = torch.as_tensor(res, device="cuda")
                 stv.res_value = torch.as_tensor(val, device="cuda")
             pv.run(stv, outv, wsv, args.warmup, use_graph=True)
-            wall_v, sc_v, prof_v = timed_run(pv, stv, outv, wsv, args.steps, use_graph=False, profile=True)
+            wall_v, sc_v, _ = timed_run(pv, stv, outv, wsv, args.steps, use_graph=False, profile="pair")
             evv = int(sc_v[mxe.S_TOTAL_EVALS])
+            _, _, prof_v = timed_run(pv, stv, outv, wsv, BREAKDOWN_STEPS, use_graph=False, profile=True)
             result["variants"][name] = dict(
                 value=n * evv / wall_v, ms_per_step=wall_v / args.steps * 1e3, evals=evv,
                 status=int(sc_v[mxe.S_STATUS]),

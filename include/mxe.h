@@ -297,12 +297,24 @@ typedef enum {
     MXE_NPROF = 6
 } mxe_kernel;
 
-/* Profiling switch (instrumentation, not part of the method). With on != 0,
- * later calls launch eagerly (mxe_run ignores use_graph) and bracket each
- * launch of every kernel family with HIP events recorded on the launch
- * stream. mxe_profile_read waits for those events and returns, per family,
- * the summed duration in ms and the number of launches since the previous
- * read (arrays of MXE_NPROF entries, caller-owned host memory). */
+/* Profiling modes of mxe_profile. */
+enum {
+    MXE_PROFILE_OFF = 0,   /* no events                                           */
+    MXE_PROFILE_ALL = 1,   /* every kernel family bracketed                       */
+    MXE_PROFILE_PAIR = 2   /* only the pair kernel bracketed (two events per
+                              evaluation: the least instrumentation that still
+                              times the dominant kernel)                         */
+};
+
+/* Profiling switch (instrumentation, not part of the method). With a mode
+ * other than MXE_PROFILE_OFF, later calls launch eagerly (mxe_run ignores
+ * use_graph) and bracket each launch of the selected kernel families with
+ * HIP events recorded on the launch stream; every event is a point where the
+ * stream's queue drains, so fewer families cost less. mxe_profile_read waits
+ * for those events and returns, per family, the summed duration in ms and
+ * the number of launches since the previous read (arrays of MXE_NPROF
+ * entries, caller-owned host memory; zero for families not bracketed).
+ * Errors: MXE_EINVAL for a null plan or an unknown mode. */
 mxe_status mxe_profile(mxe_plan* plan, int on);
 mxe_status mxe_profile_read(mxe_plan* plan, double* ms, int64_t* launches);
 

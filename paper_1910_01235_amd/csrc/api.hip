@@ -62,6 +62,7 @@ struct mxe_plan {
     std::vector<const void*> graph_key;
     // profiling: event pairs bracketing launches, per kernel family
     bool prof_on = false;
+    bool prof_pair_only = false;  // MXE_PROFILE_PAIR: only the pair kernel is bracketed
     struct ProfMark {
         int family;
         size_t start, end;  // indices into prof_events
@@ -544,6 +545,11 @@ void timed(mxe_plan* P, int family, hipStream_t s, F&& launch, bool chain = fals
         launch();
         return;
     }
+    if (P->prof_pair_only && family != MXE_K_PAIR) {
+        launch();
+        P->prof_last = -1;  // an unbracketed launch breaks the chain
+        return;
+    }
     const long start = (chain && P->prof_last >= 0) ? P->prof_last : prof_record(P, s);
     launch();
     const long end = start >= 0 ? prof_record(P, s) : -1;
@@ -672,7 +678,10 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
 
 extern "C" mxe_status mxe_profile(mxe_plan* P, int on) {
     if (!P) return fail(MXE_EINVAL, "null plan");
-    P->prof_on = on != 0;
+    if (on != MXE_PROFILE_OFF && on != MXE_PROFILE_ALL && on != MXE_PROFILE_PAIR)
+        return fail(MXE_EINVAL, "profile mode must be MXE_PROFILE_OFF, _ALL or _PAIR");
+    P->prof_on = on != MXE_PROFILE_OFF;
+    P->prof_pair_only = on == MXE_PROFILE_PAIR;
     P->prof_last = -1;
     return MXE_OK;
 }

@@ -23,6 +23,7 @@ S_F, S_FMAX, S_DT, S_TIME, S_SUMX, S_UPDATES, S_CONVERGED, S_EVALS, S_STATUS, S_
     S_TOTAL_EVALS, S_PAIRS, S_PAIR_EVALS, S_RESERVOIR = range(14)
 K_PAIR, K_DENSITY, K_FORCE, K_BUILD, K_FIRE, K_MASTER = range(6)
 KERNEL_FAMILIES = ["pair", "density", "force", "build", "fire", "master"]
+PROFILE_OFF, PROFILE_ALL, PROFILE_PAIR = 0, 1, 2  # mxe_profile modes
 STAT_NONFINITE, STAT_X_RANGE, STAT_RHO, STAT_SIGMA_MIN, STAT_KMAX, STAT_TEMP, STAT_PAIRS, \
     STAT_BONDS, STAT_SIGMA_CAP = (1 << k for k in range(9))
 FATAL_STATUS = STAT_NONFINITE | STAT_X_RANGE | STAT_RHO | STAT_KMAX | STAT_PAIRS | STAT_BONDS | \
@@ -312,8 +313,11 @@ class Plan:
         _check(lib().mxe_run(self._h, C.byref(a), C.byref(o), int(n_steps), int(bool(use_graph)),
                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
 
-    def profile(self, on: bool):
-        _check(lib().mxe_profile(self._h, int(bool(on))))
+    def profile(self, on):
+        """True: every kernel family bracketed by HIP events; "pair": only the pair
+        kernel (the least instrumentation); False: off."""
+        mode = PROFILE_PAIR if on == "pair" else (PROFILE_ALL if on else PROFILE_OFF)
+        _check(lib().mxe_profile(self._h, mode))
 
     def profile_read(self):
         """{family: (summed ms, launches)} since the previous read (waits for the events)."""

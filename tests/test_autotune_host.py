@@ -37,3 +37,18 @@ def test_plan_validates_launch_shapes():
         mxe.Plan(w.systems, w.eam, w.params, force_lanes=24)
     with pytest.raises(mxe.MxeError, match="pair_block"):
         mxe.Plan(w.systems, w.eam, w.params, pair_block=512)
+
+
+def test_profile_modes_are_validated():
+    import os
+    if not os.path.exists(mxe.LIB_PATH):
+        pytest.skip("libmxe.so not built")
+    w = L.config0(0)
+    plan = mxe.Plan(w.systems, w.eam, w.params)
+    for mode in (mxe.PROFILE_OFF, mxe.PROFILE_ALL, mxe.PROFILE_PAIR):
+        assert mxe.lib().mxe_profile(plan._h, mode) == 0
+    assert mxe.lib().mxe_profile(plan._h, 3) != 0
+    assert mxe.lib().mxe_profile(plan._h, -1) != 0
+    plan.profile("pair")
+    plan.profile(True)
+    plan.profile(False)
