@@ -121,7 +121,8 @@ struct Dev {
     double4* cell_rec; // (qx, qy, qz, sigma) of the same entries
     int *cell_of, *slot_of;
     int *chunk_up, *chunk_off;
-    int2* acell;       // [0].x: number of cells in use; [1 + b]: (system, global cell)
+    int2* acell;       // [0].x: number of cells in use; [0].y: 1 while any system's lists
+                       // are being rebuilt; [1 + b]: (system, global cell)
     int *nbr, *nbr_cnt, *nbr_lo, *pid, *half_off;
     int *pair_i, *pair_j;
     int* pnew;         // per pair: its number after the renumbering by geometric class
@@ -178,6 +179,7 @@ __device__ inline void finish_build(const Dev& d, int s) {
     if (!c.rebuild) return;
     c.n_rebuilds += 1;
     c.rebuild = 0;
+    d.acell[0].y = 0;  // set again by the next system that needs a rebuild
     c.drift_bits = 0ull;
     c.widen_bits = 0ull;
     d.scalars[(int64_t)s * MXE_NSCALARS + MXE_S_PAIRS] = (double)c.n_pairs;

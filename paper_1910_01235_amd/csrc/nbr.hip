@@ -89,6 +89,7 @@ __global__ void k_sys_init(Dev d) {
         c.drift_bits = 0ull;
         c.widen_bits = 0ull;
     }
+    if (c.rebuild) d.acell[0].y = 1;  // the neighbour search runs
     c.status = 0;
     c.n_rebuilds = 0;
     c.total_evals = 0;
@@ -162,7 +163,10 @@ __global__ __launch_bounds__(kChunk) void k_bin(Dev d, Model m) {
     SysCtl& c = d.ctl[ch.sys];
     if (!c.rebuild) {
         if (!lists_expired(c, m)) return;
-        if (threadIdx.x == 0) c.rebuild = 1;  // the same value from every block
+        if (threadIdx.x == 0) {  // the same values from every block
+            c.rebuild = 1;
+            d.acell[0].y = 1;
+        }
     }
     const int i = ch.start + threadIdx.x;
     if (i >= ch.end) return;
@@ -292,7 +296,10 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // The cells in use (count read from the table) are dealt to the XCDs in
     // contiguous ranges; the blocks of an XCD stride through their range.
-    const int na = d.acell[0].x;
+    // With no system rebuilding, every block leaves after one load.
+    const int2 a0 = d.acell[0];
+    if (a0.y == 0) return;
+    const int na = a0.x;
     const int per = (na + kXcd - 1) / kXcd;
     const int x0 = (int)(blockIdx.x % kXcd) * per, x1 = min(na, x0 + per);
     const int nq = (int)gridDim.x / kXcd;
