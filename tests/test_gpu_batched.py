@@ -135,7 +135,7 @@ def test_autotuned_shapes_keep_results(mx, tmp_path):
     p = dict(L.DEFAULT_PARAMS)
     ref = None
     for g in autotune.GATHER_LANES:
-        for b in (64, 256):
+        for b in autotune.PAIR_BLOCKS:
             f = autotune.GATHER_LANES[(autotune.GATHER_LANES.index(g) + 1) % len(autotune.GATHER_LANES)]
             plan = mx.Plan([s], L.DEFAULT_EAM, p, gather_lanes=g, force_lanes=f, pair_block=b)
             st, out, ws = plan.state([s]), plan.out(), plan.workspace()
