@@ -52,7 +52,7 @@ struct mxe_plan {
     int64_t n_sites = 0, n_cells = 0, pair_cap_total = 0;
     // workspace layout (byte offsets)
     size_t o_sys, o_ctl, o_chunks, o_pchunks, o_site_sys, o_cell_count, o_cell_start, o_cell_sites, o_cell_rec;
-    size_t o_cell_of, o_slot_of, o_chunk_up, o_chunk_off, o_acell;
+    size_t o_cell_of, o_slot_of, o_chunk_up, o_acell;
     size_t o_nbr, o_cnt, o_lo, o_pid, o_hoff, o_pi, o_pj, o_pnew, o_fblk, o_dblk, o_G, o_A, o_B;
     size_t o_v, o_qr, o_sref, o_emit, o_srec, o_bond, o_nbond, o_part, o_part_sub;
     size_t ws_bytes = 0;
@@ -348,7 +348,6 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     P->o_cell_of = take(sizeof(int) * N);
     P->o_slot_of = take(sizeof(int) * N);
     P->o_chunk_up = take(sizeof(int) * P->chunks.size());
-    P->o_chunk_off = take(sizeof(int) * P->chunks.size());
     P->o_acell = take(sizeof(int2) * (P->n_cells + 1));
     P->o_nbr = take(sizeof(int) * N * p.k_max);
     P->o_cnt = take(sizeof(int) * N);
@@ -444,7 +443,6 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.cell_of = (int*)(w + P->o_cell_of);
     D.slot_of = (int*)(w + P->o_slot_of);
     D.chunk_up = (int*)(w + P->o_chunk_up);
-    D.chunk_off = (int*)(w + P->o_chunk_off);
     D.acell = (int2*)(w + P->o_acell);
     D.nbr = (int*)(w + P->o_nbr);
     D.nbr_cnt = (int*)(w + P->o_cnt);

@@ -120,7 +120,7 @@ struct Dev {
     int* cell_sites;   // 4 * site index + site type, grouped by cell, N entries
     double4* cell_rec; // (qx, qy, qz, sigma) of the same entries
     int *cell_of, *slot_of;
-    int *chunk_up, *chunk_off;
+    int* chunk_up;     // per site chunk: owned (upper) pairs found by the build
     int2* acell;       // [0].x: number of cells in use; [0].y: 1 while any system's lists
                        // are being rebuilt; [1 + b]: (system, global cell)
     int *nbr, *nbr_cnt, *nbr_lo, *pid, *half_off;

@@ -21,12 +21,13 @@
 //                ballot and sorted (bitonic, in registers); at the start of a
 //                call also the bonds (same-type sites closer than r_bond, sorted);
 //                per-chunk count of "upper" neighbours (larger index)
-//   k_scan       per system: offsets of the chunks' upper counts; pair count;
-//                clears the upper and cell counts for the next build
 //   k_half       per chunk: offset of each site's first owned pair (each
-//                unordered pair is owned by its lower site)
+//                unordered pair is owned by its lower site), from the upper
+//                counts of the system's earlier chunks; the system's pair count;
+//                clears the cell counts for the next build
 //   k_pid        per site: pair id of every row entry (binary search in the
-//                sorted row of the other end); pair endpoint arrays
+//                sorted row of the other end); pair endpoint arrays; clears the
+//                chunk's upper count for the next build
 //   k_build_done per system: clear the flag, count the build (within a
 //                relaxation the following k_control does this instead)
 #include "mxe_internal.h"
@@ -511,38 +512,36 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan(Dev d) {
-    __shared__ int lds[1024];
-    const int s = blockIdx.x;
-    if (!d.ctl[s].rebuild) return;
-    const SysDesc& S = d.sys[s];
-    const int nch = S.n_chunks;
-    const int per = (nch + 1023) / 1024;
-    const int a = min(nch, (int)threadIdx.x * per), b = min(nch, a + per);
-    int sum = 0;
-    for (int c = a; c < b; ++c) sum += d.chunk_up[S.chunk_first + c];
-    int total;
-    int run = block_excl_scan_1024(sum, lds, total);
-    for (int c = a; c < b; ++c) {
-        d.chunk_off[S.chunk_first + c] = run;
-        run += d.chunk_up[S.chunk_first + c];
-        d.chunk_up[S.chunk_first + c] = 0;  // the next build counts afresh
-    }
-    if (threadIdx.x == 0) {
-        d.ctl[s].n_pairs = total;
-        if (total > S.pair_cap) atomicOr(&d.ctl[s].status, MXE_STAT_PAIRS);
-    }
-    for (int64_t c = S.cell_off + threadIdx.x; c < S.cell_off + S.n_cells; c += 1024) d.cell_count[c] = 0;
-}
-
 // Per chunk: each site's first owned pair = chunk offset + in-chunk prefix.
 __global__ __launch_bounds__(kChunk) void k_half(Dev d) {
     __shared__ int lds[kChunk];
+    __shared__ int wsum[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
-    if (!d.ctl[ch.sys].rebuild) return;
-    const int i = ch.start + threadIdx.x;
+    SysCtl& c = d.ctl[ch.sys];
+    if (!c.rebuild) return;
+    const SysDesc& S = d.sys[ch.sys];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+    // the chunk's first owned pair: the upper counts of the system's earlier
+    // chunks (an integer sum, so its order does not matter)
+    const int b = (int)blockIdx.x - S.chunk_first;
+    int pre = 0;
+    for (int k = t; k < b; k += kChunk) pre += d.chunk_up[S.chunk_first + k];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) pre += __shfl_xor(pre, o);
+    if (lane == 0) wsum[wave] = pre;
+    // the cell counts are not read again in this build: clear them for the next
+    for (int64_t cc = (int64_t)b * kChunk + t; cc < S.n_cells; cc += (int64_t)S.n_chunks * kChunk)
+        d.cell_count[S.cell_off + cc] = 0;
+    __syncthreads();
+    int chunk_off = 0;
+    for (int w = 0; w < kChunk / kWave; ++w) chunk_off += wsum[w];
+    if (t == 0 && b == S.n_chunks - 1) {  // the system's last chunk: its pair count
+        const int total = chunk_off + d.chunk_up[blockIdx.x];
+        c.n_pairs = total;
+        if (total > S.pair_cap) atomicOr(&c.status, MXE_STAT_PAIRS);
+    }
+    const int i = ch.start + t;
     const int u = i < ch.end ? d.nbr_cnt[i] - d.nbr_lo[i] : 0;
-    const int t = threadIdx.x;
     lds[t] = u;
     __syncthreads();
     for (int o = 1; o < kChunk; o <<= 1) {
@@ -551,7 +550,7 @@ __global__ __launch_bounds__(kChunk) void k_half(Dev d) {
         lds[t] += v;
         __syncthreads();
     }
-    if (i < ch.end) d.half_off[i] = d.chunk_off[blockIdx.x] + lds[t] - u;
+    if (i < ch.end) d.half_off[i] = chunk_off + lds[t] - u;
 }
 
 // One wavefront per site, lanes over its row: the pair id of an entry (i, j)
@@ -572,6 +571,7 @@ __global__ __launch_bounds__(kPidThreads) void k_pid(Dev d) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int K = d.K;
     bool bad = false;
+    if (threadIdx.x == 0) d.chunk_up[cb] = 0;  // read for the last time by k_half: the next build counts afresh
     for (int i = ch.start + wave; i < ch.end; i += kPidThreads / kWave) {
         const int cnt = d.nbr_cnt[i], lo = d.nbr_lo[i], hoff = d.half_off[i];
         const int* row = d.nbr + (int64_t)i * K;
@@ -740,7 +740,6 @@ void launch_build(const Dev& d, const Model& m, bool bonds, bool finish, hipStre
         case 128: k_nbr<2><<<gc, kChunk, 0, s>>>(d, m, nb); break;
         default: k_nbr<4><<<gc, kChunk, 0, s>>>(d, m, nb); break;
     }
-    k_scan<<<d.n_sys, 1024, 0, s>>>(d);
     k_half<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_pid<<<xcd_grid(d.n_chunks), kPidThreads, 0, s>>>(d);
     k_pair_order<<<d.n_pchunks, kOrderThreads, 0, s>>>(d);
