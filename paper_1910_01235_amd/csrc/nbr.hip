@@ -587,9 +587,10 @@ __global__ __launch_bounds__(kPidThreads) void k_pid(Dev d) {
                     d.pair_j[p] = j;
                 }
             } else {
+                // i > j lies in j's upper part [lo_j, cnt_j): search only there
                 const int* rj = d.nbr + (int64_t)j * K;
-                const int cj = d.nbr_cnt[j];
-                int l = 0, h = cj;
+                const int cj = d.nbr_cnt[j], lj = d.nbr_lo[j];
+                int l = lj, h = cj;
                 while (l < h) {
                     const int mid = (l + h) >> 1;
                     if (rj[mid] < i) l = mid + 1; else h = mid;
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(kPidThreads) void k_pid(Dev d) {
                     prow[k] = -1;
                     continue;
                 }
-                local = d.half_off[j] + (l - d.nbr_lo[j]);
+                local = d.half_off[j] + (l - lj);
             }
             prow[k] = (local < S.pair_cap) ? (int)(S.pair_base + local) : -1;
         }
