@@ -567,14 +567,17 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
 //                       + 3 kT / sigma_i,   <g>_si = (d<g>/dsigma_i) / sigma_i
 //   mu_i = sum_j da_ij/dx_i <phi> + db_i/dx_i sum_j (A_j <f> + B_j f0)
 //          + dc_i/dx_i G_i - 3 kT dw_i/dx_i ln sigma_i
-// Force gather layout: kLPS lanes per site; inside them, groups of four lanes
-// share one row entry, each lane loading a quarter of the pair's force block
-// (slots 4q .. 4q+3) and the neighbour's record. A wave-wide block load then
-// touches one cache line per entry instead of one per lane.
-constexpr int kQ = 4;
+// Force gather layout: kLPS lanes per site; inside them, groups of kQ lanes
+// share one row entry, each lane loading its part of the pair's force block
+// (4 / kQ quarters of four slots: 4q' .. 4q'+3) and the neighbour's record.
+// A wave-wide block load then touches one cache line per entry instead of one
+// per lane. FP64 blocks (128 B) take four lanes per entry; the 64-B FP32
+// blocks take two, so twice the entries are in flight for the same registers.
+template <typename T>
+constexpr int kQ = sizeof(T) == sizeof(double) ? 4 : 2;
 
 template <typename T, int kLPS>
-__global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
+__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) void k_force(Dev d, Model m) {
     constexpr int kGroups = kChunk / kLPS;
     __shared__ double red[kGroups][6];
     // kForceSplit blocks per site chunk, each taking a contiguous part of it
@@ -591,10 +594,12 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
     const double kT = S.kT;
     const bool site_T = d.T_site != nullptr;
     const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
-    const int q = sub % kQ, es = sub / kQ;  // quarter of the block; entry slot
+    constexpr int kQL = kQ<T>;                // lanes per entry
+    constexpr int kQuarters = 4 / kQL;        // quarters of the block per lane
+    const int q = sub % kQL, es = sub / kQL;  // the lane's part of the block; entry slot
     const Vec16<T>* fblk = (const Vec16<T>*)d.fblk;
     constexpr int per = kFBlk / Vec16<T>::n;  // vectors per block
-    constexpr int perq = per / kQ;            // vectors per quarter
+    constexpr int perq = per / kQL;           // vectors per lane
     const int K = d.K;
     double pe = 0.0, pfmax = 0.0, pfv = 0.0, pff = 0.0, pvv = 0.0, psx = 0.0;
     int bad = 0;
@@ -618,14 +623,14 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
             jn = row[es];
             pn = prow[es];
         }
-        for (int k = es; k < cnt; k += kLPS / kQ) {
+        for (int k = es; k < cnt; k += kLPS / kQL) {
             const int j = jn, p = pn;
-            if (k + kLPS / kQ < cnt) {
-                jn = row[k + kLPS / kQ];
-                pn = prow[k + kLPS / kQ];
+            if (k + kLPS / kQL < cnt) {
+                jn = row[k + kLPS / kQL];
+                pn = prow[k + kLPS / kQL];
             }
             if (p < 0) continue;
-            T mq[4];
+            T mq[4 * kQuarters];
 #pragma unroll
             for (int v = 0; v < perq; ++v) {
                 const Vec16<T> b = fblk[(int64_t)p * per + q * perq + v];
@@ -664,30 +669,35 @@ __global__ __launch_bounds__(kChunk) void k_force(Dev d, Model m) {
             const double hA = Ahi * bj + Aj * bhat_i;
             const double hB = Bhi * bj + Bj * bhat_i;
             const double sg = j > i ? 1.0 : -1.0;
-            const double m0 = (double)mq[0], m1 = (double)mq[1], m2 = (double)mq[2], m3 = (double)mq[3];
-            if (q == 0) {         // <phi>, grad <phi>
-                ep += aij * m0;
-                mu += dadx * m0;
-                const double c = sg * ahat;
-                fx += c * m1;
-                fy += c * m2;
-                fz += c * m3;
-            } else if (q == 1) {  // lo-end width term of <phi>, <f>, grad <f> (x, y)
-                if (sg > 0.0) fsg += ahat * m0;
-                mu += db_i * Aj * m1;
-                const double c = sg * hA;
-                fx += c * m2;
-                fy += c * m3;
-            } else if (q == 2) {  // grad <f> (z), lo-end width term of <f>, f0, grad f0 (x)
-                fz += sg * hA * m0;
-                if (sg > 0.0) fsg += hA * m1;
-                mu += db_i * Bj * m2;
-                fx += sg * hB * m3;
-            } else {              // grad f0 (y, z), hi-end width terms of <phi>, <f>
-                const double c = sg * hB;
-                fy += c * m0;
-                fz += c * m1;
-                if (sg < 0.0) fsg += ahat * m2 + hA * m3;
+#pragma unroll
+            for (int u = 0; u < kQuarters; ++u) {
+                const int qd = q * kQuarters + u;  // the quarter of the block
+                const double m0 = (double)mq[4 * u], m1 = (double)mq[4 * u + 1];
+                const double m2 = (double)mq[4 * u + 2], m3 = (double)mq[4 * u + 3];
+                if (qd == 0) {         // <phi>, grad <phi>
+                    ep += aij * m0;
+                    mu += dadx * m0;
+                    const double c = sg * ahat;
+                    fx += c * m1;
+                    fy += c * m2;
+                    fz += c * m3;
+                } else if (qd == 1) {  // lo-end width term of <phi>, <f>, grad <f> (x, y)
+                    if (sg > 0.0) fsg += ahat * m0;
+                    mu += db_i * Aj * m1;
+                    const double c = sg * hA;
+                    fx += c * m2;
+                    fy += c * m3;
+                } else if (qd == 2) {  // grad <f> (z), lo-end width term of <f>, f0, grad f0 (x)
+                    fz += sg * hA * m0;
+                    if (sg > 0.0) fsg += hA * m1;
+                    mu += db_i * Bj * m2;
+                    fx += sg * hB * m3;
+                } else {              // grad f0 (y, z), hi-end width terms of <phi>, <f>
+                    const double c = sg * hB;
+                    fy += c * m0;
+                    fz += c * m1;
+                    if (sg < 0.0) fsg += ahat * m2 + hA * m3;
+                }
             }
         }
         fx = group_sum<kLPS>(fx);
