@@ -50,10 +50,10 @@ BREAKDOWN_STEPS = 2
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="6a43875cce35e3e7",
-    pair=dict(fetch_kib=159825.2, write_kib=1019787.0),
-    force=dict(fetch_kib=900770.1, write_kib=13650.9),
-    density=dict(fetch_kib=182522.2, write_kib=32831.9),
+    sources_sha256_16="0785eb5fa3415aa0",
+    pair=dict(fetch_kib=159801.2, write_kib=1019787.0),
+    force=dict(fetch_kib=900847.6, write_kib=13649.6),
+    density=dict(fetch_kib=172861.2, write_kib=26944.5),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 

@@ -469,6 +469,12 @@ void k_pair(Dev d, Model m) {
 
 // Gathers run LPS lanes per site, so one wavefront serves 64 / LPS sites at a
 // time and keeps that many sites' loads in flight.
+// Density gather: row entries per lane in flight, so that a site's lanes hold
+// 64 entries at once (one iteration for most rows). Measured with 8 lanes
+// (the tuned width): 8 entries per lane beat 2, 4 and 6 (82 VGPRs in FP64,
+// 5 waves per SIMD instead of 8).
+template <int kLPS>
+constexpr int kDensDepth = kLPS >= 64 ? 1 : 64 / kLPS;
 // kLPS (8, 16, 32 or 64) is chosen per plan (tuned); kGroups sites run per block.
 
 template <int LPS>
@@ -496,21 +502,35 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
         const int* row = d.nbr + (int64_t)i * K;
         const int* prow = d.pid + (int64_t)i * K;
         double rb = 0.0, r0 = 0.0;
-        int jn = 0, pn = -1;  // next entry, loaded one iteration ahead
-        if (sub < cnt) {
-            jn = row[sub];
-            pn = prow[sub];
-        }
-        for (int k = sub; k < cnt; k += kLPS) {
-            const int j = jn, p = pn;
-            if (k + kLPS < cnt) {
-                jn = row[k + kLPS];
-                pn = prow[k + kLPS];
+        // a lane takes kDensDepth entries per iteration (k, k + kLPS, ...): their
+        // loads are in flight together and they are added in entry order
+        // (loading the next entries' (j, pair id) ahead measured slower in FP64)
+        for (int k = sub; k < cnt; k += kDensDepth<kLPS> * kLPS) {
+            int jc[kDensDepth<kLPS>], pc[kDensDepth<kLPS>];
+#pragma unroll
+            for (int u = 0; u < kDensDepth<kLPS>; ++u) {
+                const int kk = k + u * kLPS;
+                jc[u] = 0;
+                pc[u] = -1;
+                if (kk < cnt) {
+                    jc[u] = row[kk];
+                    pc[u] = prow[kk];
+                }
             }
-            if (p < 0) continue;
-            const double bj = d.emit[j];
-            rb += bj * (double)dblk[2 * (int64_t)p];
-            r0 += bj * (double)dblk[2 * (int64_t)p + 1];
+            double bj[kDensDepth<kLPS>], fa[kDensDepth<kLPS>], fb[kDensDepth<kLPS>];
+#pragma unroll
+            for (int u = 0; u < kDensDepth<kLPS>; ++u) {  // an absent entry reads pair 0 and site 0, adds nothing
+                const int64_t pp = pc[u] < 0 ? 0 : pc[u];
+                bj[u] = d.emit[pc[u] < 0 ? 0 : jc[u]];
+                fa[u] = (double)dblk[2 * pp];
+                fb[u] = (double)dblk[2 * pp + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kDensDepth<kLPS>; ++u) {
+                if (pc[u] < 0) continue;
+                rb += bj[u] * fa[u];
+                r0 += bj[u] * fb[u];
+            }
         }
         rb = group_sum<kLPS>(rb);
         r0 = group_sum<kLPS>(r0);
