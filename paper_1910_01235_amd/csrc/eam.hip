@@ -362,6 +362,8 @@ __device__ inline void pair_all_moments(const Model& m, const SysDesc& S, double
     }
 }
 
+// The FP64 kernels are held at 128 VGPRs (4 waves per SIMD): the 27-node
+// kernel's node sums would otherwise take 131 and drop to 3 waves.
 template <typename T, int kBS, int kRule>
 __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1)))
 void k_pair(Dev d, Model m) {
@@ -596,6 +598,8 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
 template <typename T>
 constexpr int kQ = sizeof(T) == sizeof(double) ? 4 : 2;
 
+// At most 128 VGPRs (4 waves per SIMD): the FP32 variant would otherwise take
+// 129 and drop to 3 waves; fewer waves measured slower in every variant tried.
 template <typename T, int kLPS>
 __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) void k_force(Dev d, Model m) {
     constexpr int kGroups = kChunk / kLPS;
