@@ -133,17 +133,21 @@ def test_autotuned_shapes_keep_results(mx, tmp_path):
     from paper_1910_01235_amd import autotune
     s = L.jitter(L.vacancy_bulk(6, 4, 900.0, 5), 6, xr=(0.3, 0.9))
     p = dict(L.DEFAULT_PARAMS)
-    ref = None
-    for g in autotune.GATHER_LANES:
-        for b in autotune.PAIR_BLOCKS:
-            f = autotune.GATHER_LANES[(autotune.GATHER_LANES.index(g) + 1) % len(autotune.GATHER_LANES)]
-            plan = mx.Plan([s], L.DEFAULT_EAM, p, gather_lanes=g, force_lanes=f, pair_block=b)
-            st, out, ws = plan.state([s]), plan.out(), plan.workspace()
-            plan.evaluate(st, out, ws)
-            f = torch.stack([out.fx, out.fy, out.fz, out.fsigma, out.mu], 1).cpu().numpy()
-            if ref is None:
-                ref = f
-            assert np.abs(f - ref).max() <= 1e-13 * np.abs(ref).max(), (g, b)
+    # FP64 shapes agree to rounding; FP32-mixed shapes store the moments in FP32
+    # (two lanes per force-gather entry) and agree to that precision
+    for prec, tol in (("fp64", 1e-13), ("fp32", 1e-6)):
+        ref = None
+        for g in autotune.GATHER_LANES:
+            for b in autotune.PAIR_BLOCKS:
+                f = autotune.GATHER_LANES[(autotune.GATHER_LANES.index(g) + 1) % len(autotune.GATHER_LANES)]
+                plan = mx.Plan([s], L.DEFAULT_EAM, p, precision=prec, gather_lanes=g, force_lanes=f,
+                               pair_block=b)
+                st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+                plan.evaluate(st, out, ws)
+                f = torch.stack([out.fx, out.fy, out.fz, out.fsigma, out.mu], 1).cpu().numpy()
+                if ref is None:
+                    ref = f
+                assert np.abs(f - ref).max() <= tol * np.abs(ref).max(), (prec, g, b)
     cache = autotune.Cache(str(tmp_path / "tune.json"))
     params, hit = autotune.tuned_params([s], L.DEFAULT_EAM, p, "fp64", cache=cache, reps=2)
     assert params["gather_lanes"] in autotune.GATHER_LANES
