@@ -280,15 +280,22 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
     const T other[3] = {R2[1] + R2[2], R2[0] + R2[2], R2[0] + R2[1]};
 #pragma unroll
     for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
-    T ws[2][2] = {{T(0), T(0)}, {T(0), T(0)}};  // [end][shape]: sum c d_a g'/r
+    // Node sums by offset. A node's gradient term is g'/r d_b, where d_b = R_b
+    // off the node's axis and R_a + c h_e on it, and its width term is
+    // c d_a g'/r; with U[q][e] = sum of g'/r over end e's six nodes and
+    // P[q][e][a] = sum over c of c g'/r on axis a, the gradient is
+    // R_b (U_lo + U_hi) + h_lo P_lo,b + h_hi P_hi,b and end e's width sum is
+    // R.P_e + h_e U_e (q: 0 = phi, 1 = f). Two sums per node and shape
+    // instead of four.
+    const T hh[2] = {kSqrt6 * (T)si, kSqrt6 * (T)sj};
+    T P[2][2][3] = {}, U[2][2] = {};
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-        const T h = kSqrt6 * (T)(e == 0 ? si : sj);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
 #pragma unroll
             for (int c = -1; c <= 1; c += 2) {
-                const T da = R[a] + T(c) * h;
+                const T da = R[a] + T(c) * hh[e];
                 const T r2 = other[a] + da * da;
                 if (r2 < rc2 && r2 > T(0)) {
                     const T rinv = Math<T>::rsq(r2);
@@ -298,24 +305,32 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
                     const T cp = W * dgp * rinv, cf = W * dgf * rinv;
                     out[M_PHI] += W * gp;
                     out[M_F] += W * gf;
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        const T db = b == a ? da : R[b];
-                        out[M_GPHI + b] += cp * db;
-                        out[M_GF + b] += cf * db;
+                    U[0][e] += cp;
+                    U[1][e] += cf;
+                    if (c > 0) {
+                        P[0][e][a] += cp;
+                        P[1][e][a] += cf;
+                    } else {
+                        P[0][e][a] -= cp;
+                        P[1][e][a] -= cf;
                     }
-                    ws[e][0] += cp * (T(c) * da);
-                    ws[e][1] += cf * (T(c) * da);
                 }
             }
         }
     }
-    // (d<g>/dsigma_e) / sigma_e = sqrt(6) ws / sigma_e
+    // (d<g>/dsigma_e) / sigma_e = sqrt(6) (width sum of end e) / sigma_e
     const T fi = kSqrt6 / (T)si, fj = kSqrt6 / (T)sj;
-    out[M_SPHI] = ws[0][0] * fi;
-    out[M_SF] = ws[0][1] * fi;
-    out[M_SPHI_HI] = ws[1][0] * fj;
-    out[M_SF_HI] = ws[1][1] * fj;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int g = q == 0 ? M_GPHI : M_GF;
+        const T tot = U[q][0] + U[q][1];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) out[g + b] = R[b] * tot + hh[0] * P[q][0][b] + hh[1] * P[q][1][b];
+        const T w0 = R[0] * P[q][0][0] + R[1] * P[q][0][1] + R[2] * P[q][0][2] + hh[0] * U[q][0];
+        const T w1 = R[0] * P[q][1][0] + R[1] * P[q][1][1] + R[2] * P[q][1][2] + hh[1] * U[q][1];
+        out[q == 0 ? M_SPHI : M_SF] = w0 * fi;
+        out[q == 0 ? M_SPHI_HI : M_SF_HI] = w1 * fj;
+    }
     const T r2c = other[0] + R2[0];
     if (r2c < rc2 && r2c > T(0)) {  // the density at the mean positions
         const T rinv = Math<T>::rsq(r2c);
