@@ -32,7 +32,3 @@ def test_pd_nanowire_site_counts():
     assert abs(n_host / g["n_host"] - 1) < 0.01
     assert abs(n_oct / g["n_oct"] - 1) < 0.01
 
-
-def test_weak_scaling_total():
-    g = G["parallel_weak"]
-    assert g["per_proc"] * g["procs"] == g["total"]
