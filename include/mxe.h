@@ -23,8 +23,10 @@
  *   Ownership: the caller allocates and owns every device buffer (state,
  *     outputs, workspace). The library never allocates device memory; a plan
  *     owns host memory, one HIP stream used only to record graphs, and the
- *     graphs it records. All device pointers must be valid for the current
- *     HIP device.
+ *     graphs it records. The one exception is mxe_run_noalloc's fixed scratch
+ *     array, held per device from the library's first use there until the
+ *     process ends. All device pointers must be valid for the current HIP
+ *     device.
  *   Asynchrony: every call only enqueues work on `stream` (a hipStream_t
  *     passed as void*, 0 = the null stream) and returns at once. Return codes
  *     report argument and plan errors; errors the device detects are written
@@ -249,6 +251,10 @@ int64_t mxe_plan_sites(const mxe_plan* plan);
  * (sites, or cells of its box), MXE_EINVAL for a bad box or temperature. A
  * system's results do not depend on its slot, its capacity or the other slots. */
 mxe_status mxe_plan_set_system(mxe_plan* plan, int slot, const mxe_system* sys);
+/* Would mxe_plan_set_system accept sys for this slot? Host-only check with the
+ * same results (MXE_OK, MXE_ERANGE: too many sites or cells for the slot,
+ * MXE_EINVAL: bad box, temperature or slot); the plan is not changed. */
+mxe_status mxe_plan_check_system(const mxe_plan* plan, int slot, const mxe_system* sys);
 /* First site of a slot; slot == n_systems gives the total. -1 if out of range. */
 int64_t mxe_plan_slot_offset(const mxe_plan* plan, int slot);
 /* Resume mode. Off (default): every call rebuilds all neighbour lists and
@@ -285,6 +291,50 @@ mxe_status mxe_step(mxe_plan* plan, const mxe_state* state, const mxe_out* out, 
  * buffers and stream) and replayed. */
 mxe_status mxe_run(mxe_plan* plan, const mxe_state* state, const mxe_out* out, int n_steps,
                    int use_graph, void* ws, size_t ws_bytes, void* stream);
+
+/* Size of the device scratch that mxe_run_noalloc uses instead of a workspace:
+ * one array per device, held from the library's first use on that device
+ * until the process ends. */
+#define MXE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): mxe_run with eager
+ * launches whose workspace is the library's own per-device scratch of
+ * MXE_NOALLOC_SCRATCH_BYTES instead of a caller buffer. The caller still owns
+ * the state and outputs. The call allocates nothing (no hipMalloc, no
+ * allocating library routine; its host-to-device copies of the plan's tables
+ * come from host memory the plan owns).
+ * Semantics: as mxe_run(use_graph = 0), except that every call starts afresh:
+ * it uploads the plan's tables and rebuilds every neighbour list and bond
+ * (resume mode is ignored), since other calls may have overwritten the scratch.
+ * Results equal mxe_run's on a caller workspace.
+ * Errors: MXE_ENOMEM if mxe_workspace_bytes of the plan exceeds
+ * MXE_NOALLOC_SCRATCH_BYTES (nothing is launched); MXE_EINVAL with profiling
+ * switched on (profiling creates events).
+ * Concurrency: all calls on one device share that device's scratch, which
+ * keeps the last call's contents; calls that overlap on one device (other
+ * streams, other threads, other plans) race and must be serialised by the
+ * caller. */
+mxe_status mxe_run_noalloc(mxe_plan* plan, const mxe_state* state, const mxe_out* out, int n_steps,
+                           void* stream);
+
+/* Workspace layout, for inspection of the neighbour and bond lists (the
+ * lists of Sec. 4, Alg. 1, and the nearest-neighbour bonds of the kinetic law,
+ * Sec. 3.1). Items, each a dense int32 array at a byte offset in the workspace:
+ *   MXE_L_NBR         [n_sites][k_max]: row i lists the neighbours j of site i
+ *                     (ascending; the first count[i] entries are valid): every
+ *                     pair with |rbar_ij| < r_c + 3 s_ij + skin at the last build
+ *                     (s_ij = sqrt(sigma_i^2 + sigma_j^2)), interstitial pairs
+ *                     excluded, plus possibly pairs within 1e-5 A of that radius
+ *   MXE_L_NBR_COUNT   [n_sites]
+ *   MXE_L_BOND        [n_sites][bond_max]: bonds of mobile site i (ascending),
+ *                     same-type sites closer than r_bond
+ *   MXE_L_BOND_COUNT  [n_sites]
+ * Global site indices (concatenated systems). Valid after a call that built the
+ * lists (every call outside resume mode) or the bonds (mxe_step, mxe_run), once
+ * the stream has synchronised. Host-only: returns the byte offset and size. */
+enum { MXE_L_NBR = 0, MXE_L_NBR_COUNT = 1, MXE_L_BOND = 2, MXE_L_BOND_COUNT = 3 };
+mxe_status mxe_plan_layout(const mxe_plan* plan, int item, size_t* offset, size_t* bytes);
 
 /* Kernel families timed by the profiling switch. */
 typedef enum {

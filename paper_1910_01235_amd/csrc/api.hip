@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -132,21 +133,43 @@ void bind_slot(mxe_plan* P, int s, const mxe_system& ms) {
 
 }  // namespace
 
+extern "C" mxe_status mxe_plan_check_system(const mxe_plan* P, int slot, const mxe_system* sys);
+
 extern "C" mxe_status mxe_plan_set_system(mxe_plan* P, int slot, const mxe_system* sys) {
+    if (!P || !sys) return fail(MXE_EINVAL, "null argument");
+    if (slot < 0 || slot >= P->n_sys) return fail(MXE_EINVAL, "slot out of range");
+    const mxe_status r = mxe_plan_check_system(P, slot, sys);
+    if (r != MXE_OK) return r;
+    bind_slot(P, slot, *sys);
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_plan_check_system(const mxe_plan* P, int slot, const mxe_system* sys) {
     if (!P || !sys) return fail(MXE_EINVAL, "null argument");
     if (slot < 0 || slot >= P->n_sys) return fail(MXE_EINVAL, "slot out of range");
     if (sys->n_sites < 0 || sys->n_sites > P->cap_sites[slot])
         return fail(MXE_ERANGE, "slot " + std::to_string(slot) + " holds at most " +
                                     std::to_string(P->cap_sites[slot]) + " sites");
-    if (sys->n_sites > 0) {
-        int64_t ncell = 0;
-        mxe_status r = slot_cells(P, *sys, slot, &ncell);
-        if (r != MXE_OK) return r;
-        if (ncell > P->cap_cells[slot])
-            return fail(MXE_ERANGE, "slot " + std::to_string(slot) + ": box needs " + std::to_string(ncell) +
-                                        " cells, capacity " + std::to_string(P->cap_cells[slot]));
+    if (sys->n_sites == 0) return MXE_OK;
+    int64_t ncell = 0;
+    mxe_status r = slot_cells(P, *sys, slot, &ncell);
+    if (r != MXE_OK) return r;
+    if (ncell > P->cap_cells[slot])
+        return fail(MXE_ERANGE, "slot " + std::to_string(slot) + ": box needs " + std::to_string(ncell) +
+                                    " cells, capacity " + std::to_string(P->cap_cells[slot]));
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_plan_layout(const mxe_plan* P, int item, size_t* offset, size_t* bytes) {
+    if (!P || !offset || !bytes) return fail(MXE_EINVAL, "null argument");
+    const size_t N = (size_t)P->n_sites;
+    switch (item) {
+        case MXE_L_NBR: *offset = P->o_nbr; *bytes = sizeof(int) * N * P->p.k_max; break;
+        case MXE_L_NBR_COUNT: *offset = P->o_cnt; *bytes = sizeof(int) * N; break;
+        case MXE_L_BOND: *offset = P->o_bond; *bytes = sizeof(int) * N * P->p.bond_max; break;
+        case MXE_L_BOND_COUNT: *offset = P->o_nbond; *bytes = sizeof(int) * N; break;
+        default: return fail(MXE_EINVAL, "unknown layout item");
     }
-    bind_slot(P, slot, *sys);
     return MXE_OK;
 }
 
@@ -671,6 +694,70 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
         P->graph_key = key;
     }
     for (int k = 0; k < n_steps; ++k) HIP_OK(hipGraphLaunch(P->graph, s));
+    return MXE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free entry point: the workspace is a library-held device array.
+// ---------------------------------------------------------------------------
+// One copy per device, allocated when the code object loads and held until the
+// process ends. Host code never passes the array's name to a kernel or a copy
+// (on the host it is only a stand-in): it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static constexpr size_t kScratchBytes = (size_t)MXE_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up once per device).
+mxe_status scratch_for_current_device(void** out) {
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MXE_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        size_t bytes = 0;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        HIP_OK(hipGetSymbolSize(&bytes, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr) % 256 != 0 || bytes < kScratchBytes)
+            return fail(MXE_EDEVICE, "scratch symbol: unexpected address or size");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MXE_OK;
+}
+
+}  // namespace
+
+extern "C" mxe_status mxe_run_noalloc(mxe_plan* P, const mxe_state* st, const mxe_out* out,
+                                      int n_steps, void* stream) {
+    if (!P) return fail(MXE_EINVAL, "null plan");
+    if (n_steps < 0) return fail(MXE_EINVAL, "n_steps < 0");
+    if (P->ws_bytes > kScratchBytes)
+        return fail(MXE_ENOMEM, "plan needs " + std::to_string(P->ws_bytes) +
+                                    " workspace bytes; the allocation-free entry point holds " +
+                                    std::to_string(kScratchBytes) + " per device");
+    if (P->prof_on) return fail(MXE_EINVAL, "profiling creates events: switch it off for mxe_run_noalloc");
+    void* ws = nullptr;
+    mxe_status r = scratch_for_current_device(&ws);
+    if (r != MXE_OK) return r;
+    Dev d;
+    r = make_dev(P, st, out, ws, kScratchBytes, &d);
+    if (r != MXE_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    // Any call on this device may have overwritten the scratch since this plan
+    // last used it: upload every table and rebuild every list and bond.
+    P->tables_ws = nullptr;
+    r = begin_call(P, d, s, true);
+    P->tables_ws = nullptr;
+    if (r != MXE_OK) return r;
+    for (int k = 0; k < n_steps; ++k) enqueue_diffusion_step(P, d, s);
+    HIP_OK(hipGetLastError());
     return MXE_OK;
 }
 

@@ -24,14 +24,16 @@ S_F, S_FMAX, S_DT, S_TIME, S_SUMX, S_UPDATES, S_CONVERGED, S_EVALS, S_STATUS, S_
 K_PAIR, K_DENSITY, K_FORCE, K_BUILD, K_FIRE, K_MASTER = range(6)
 KERNEL_FAMILIES = ["pair", "density", "force", "build", "fire", "master"]
 PROFILE_OFF, PROFILE_ALL, PROFILE_PAIR = 0, 1, 2  # mxe_profile modes
+L_NBR, L_NBR_COUNT, L_BOND, L_BOND_COUNT = range(4)  # mxe_plan_layout items
 STAT_NONFINITE, STAT_X_RANGE, STAT_RHO, STAT_SIGMA_MIN, STAT_KMAX, STAT_TEMP, STAT_PAIRS, \
     STAT_BONDS, STAT_SIGMA_CAP = (1 << k for k in range(9))
 FATAL_STATUS = STAT_NONFINITE | STAT_X_RANGE | STAT_RHO | STAT_KMAX | STAT_PAIRS | STAT_BONDS | \
     STAT_SIGMA_CAP | STAT_TEMP
 
 EXPORTED = ["mxe_default_params", "mxe_plan_create", "mxe_plan_destroy", "mxe_workspace_bytes",
-            "mxe_plan_sites", "mxe_plan_set_system", "mxe_plan_slot_offset", "mxe_plan_set_resume",
-            "mxe_evaluate", "mxe_relax", "mxe_step", "mxe_run", "mxe_profile", "mxe_profile_read",
+            "mxe_plan_sites", "mxe_plan_set_system", "mxe_plan_check_system", "mxe_plan_slot_offset",
+            "mxe_plan_set_resume", "mxe_plan_layout",
+            "mxe_evaluate", "mxe_relax", "mxe_step", "mxe_run", "mxe_run_noalloc", "mxe_profile", "mxe_profile_read",
             "mxe_status_string", "mxe_last_error"]
 
 
@@ -90,6 +92,11 @@ def lib():
         L.mxe_plan_sites.restype = C.c_int64
         L.mxe_plan_set_system.argtypes = [C.c_void_p, C.c_int, C.POINTER(System)]
         L.mxe_plan_set_system.restype = C.c_int
+        L.mxe_plan_check_system.argtypes = [C.c_void_p, C.c_int, C.POINTER(System)]
+        L.mxe_plan_check_system.restype = C.c_int
+        L.mxe_plan_layout.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_size_t),
+                                      C.POINTER(C.c_size_t)]
+        L.mxe_plan_layout.restype = C.c_int
         L.mxe_plan_slot_offset.argtypes = [C.c_void_p, C.c_int]
         L.mxe_plan_slot_offset.restype = C.c_int64
         L.mxe_plan_set_resume.argtypes = [C.c_void_p, C.c_int]
@@ -104,6 +111,9 @@ def lib():
         L.mxe_run.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Out), C.c_int, C.c_int,
                               C.c_void_p, C.c_size_t, C.c_void_p]
         L.mxe_run.restype = C.c_int
+        L.mxe_run_noalloc.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Out), C.c_int,
+                                      C.c_void_p]
+        L.mxe_run_noalloc.restype = C.c_int
         L.mxe_status_string.argtypes = [C.c_int]
         L.mxe_status_string.restype = C.c_char_p
         L.mxe_last_error.restype = C.c_char_p
@@ -260,6 +270,31 @@ class Plan:
         m = self._system(s)
         _check(lib().mxe_plan_set_system(self._h, int(slot), C.byref(m)))
 
+    def check_system(self, slot: int, s) -> bool:
+        """Would set_system(slot, s) be accepted? (host-only; raises on a bad box or T)"""
+        m = self._system(s)
+        code = lib().mxe_plan_check_system(self._h, int(slot), C.byref(m))
+        if code == -5:  # MXE_ERANGE: does not fit the slot
+            return False
+        _check(code)
+        return True
+
+    def layout(self, item: int):
+        """(byte offset, bytes) of a workspace array (L_NBR, L_NBR_COUNT, L_BOND, L_BOND_COUNT)."""
+        off, nb = C.c_size_t(), C.c_size_t()
+        _check(lib().mxe_plan_layout(self._h, int(item), C.byref(off), C.byref(nb)))
+        return int(off.value), int(nb.value)
+
+    def lists(self, ws):
+        """Host copies of the neighbour rows and bonds held in the workspace
+        (valid after a call that built them, once the stream has synchronised)."""
+        def arr(item, cols):
+            off, nb = self.layout(item)
+            a = ws[off:off + nb].view(dtype=__import__("torch").int32).cpu().numpy()
+            return a.reshape(self.n_sites, cols) if cols else a
+        return dict(nbr=arr(L_NBR, self.params.k_max), nbr_count=arr(L_NBR_COUNT, 0),
+                    bond=arr(L_BOND, self.params.bond_max), bond_count=arr(L_BOND_COUNT, 0))
+
     def set_resume(self, on: bool):
         _check(lib().mxe_plan_set_resume(self._h, int(bool(on))))
 
@@ -312,6 +347,12 @@ class Plan:
         a, o = st.abi(), out.abi()
         _check(lib().mxe_run(self._h, C.byref(a), C.byref(o), int(n_steps), int(bool(use_graph)),
                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+
+    def run_noalloc(self, st: DeviceState, out: DeviceOut, n_steps: int, stream=None):
+        """mxe_run on the library's per-device scratch (no workspace argument)."""
+        a, o = st.abi(), out.abi()
+        _check(lib().mxe_run_noalloc(self._h, C.byref(a), C.byref(o), int(n_steps),
+                                     _stream_ptr(stream)))
 
     def profile(self, on):
         """True: every kernel family bracketed by HIP events; "pair": only the pair

@@ -85,9 +85,14 @@ def pick_slot(capacities: list, free, n: int):
     return best
 
 
+# volume per site of the FCC lattice, with a margin: a slot's cell capacity is
+# sized from a cube of this volume per site
+VOLUME_PER_SITE = 1.05 * L.A0_CU ** 3 / 4.0
+
+
 def _template(capacity: int, r_min_box: float) -> L.System:
     """Placeholder system that defines a slot's capacity (slots start empty)."""
-    side = max(r_min_box, (capacity * 11.8) ** (1.0 / 3.0))
+    side = max(r_min_box, (capacity * VOLUME_PER_SITE) ** (1.0 / 3.0))
     n = capacity
     return L.System(np.zeros((n, 3)), np.full(n, 0.1), np.ones(n), np.zeros(n, np.int8),
                     (side, side, side), (True, True, True), 300.0, f"slot{capacity}")
@@ -120,11 +125,24 @@ class Server:
     def footprint_bytes(self) -> int:
         return self.ws.numel() + self.plan.n_sites * STATE_BYTES_PER_SITE
 
-    def fits(self, n: int) -> bool:
-        return n <= max(self.capacities)
+    def fits(self, s: L.System) -> bool:
+        """Does some slot (free or not) accept this system (sites and cells)?"""
+        seen = set()
+        for k, c in enumerate(self.capacities):
+            if c >= s.n and c not in seen:  # slots of one capacity accept the same systems
+                seen.add(c)
+                if self.plan.check_system(k, s):
+                    return True
+        return False
 
-    def pick_slot(self, n: int):
-        return pick_slot(self.capacities, self.free, n)
+    def pick_slot(self, s: L.System):
+        """Smallest free slot that accepts the system (by sites, then by cells), or None."""
+        free = set(self.free)
+        while True:
+            k = pick_slot(self.capacities, free, s.n)
+            if k is None or self.plan.check_system(k, s):
+                return k
+            free.discard(k)
 
     def admit(self, slot: int, s: L.System):
         torch = self.torch
@@ -160,8 +178,9 @@ class Server:
         torch = self.torch
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         n_steps_of = {r.rid: r.n_steps for r in pending}
-        rejected = [r.rid for r in pending if not self.fits(r.system.n)]
-        pending = [r for r in pending if self.fits(r.system.n)]
+        fit = {r.rid: self.fits(r.system) for r in pending}
+        rejected = [r.rid for r in pending if not fit[r.rid]]
+        pending = [r for r in pending if fit[r.rid]]
         active = {}  # slot -> [request, steps done, admitted time]
         results = []
         steps = 0
@@ -176,7 +195,7 @@ class Server:
                 if realtime and r.arrival > t:
                     keep.append(r)
                     continue
-                slot = self.pick_slot(r.system.n)
+                slot = self.pick_slot(r.system)
                 if slot is None:
                     keep.append(r)
                     continue

@@ -63,3 +63,52 @@ def test_plan_validation_needs_no_gpu():
     # fp32 workspace is smaller (FP32 moments)
     p32 = mxe.Plan(w.systems, w.eam, w.params, precision="fp32")
     assert p32.ws_bytes < plan.ws_bytes
+
+
+def test_host_only_queries():
+    """Slot checks, workspace layout and the scratch limit need no GPU."""
+    from paper_1910_01235_amd import lattice as L
+    from paper_1910_01235_amd import mxe
+    if not os.path.exists(mxe.LIB_PATH):
+        pytest.skip("libmxe.so not built")
+    w = L.config0(0)
+    plan = mxe.Plan(w.systems, w.eam, w.params)
+    # layout: rows of k_max ints, counts, bonds of bond_max ints, inside the workspace
+    items = [(mxe.L_NBR, 256 * 96 * 4), (mxe.L_NBR_COUNT, 256 * 4), (mxe.L_BOND, 256 * 16 * 4),
+             (mxe.L_BOND_COUNT, 256 * 4)]
+    for item, size in items:
+        off, nb = plan.layout(item)
+        assert nb == size and off % 256 == 0 and off + nb <= plan.ws_bytes
+    with pytest.raises(mxe.MxeError, match="layout"):
+        plan.layout(7)
+    # slot checks: sites, then cells of the box; the plan is left unchanged
+    small = L.vacancy_bulk(4, 0, 800.0, 1)
+    assert plan.check_system(0, small)
+    big = L.vacancy_bulk(5, 0, 800.0, 1)
+    assert not plan.check_system(0, big)
+    rod = small.copy()
+    rod.q = rod.q[:200]
+    rod.box = (14.46, 14.46, 2000.0)  # few sites, far more cells than the slot holds
+    rod.periodic = (True, True, False)
+    assert not plan.check_system(0, rod)
+    bad = small.copy()
+    bad.T = -1.0
+    with pytest.raises(mxe.MxeError, match="T must be positive"):
+        plan.check_system(0, bad)
+    assert plan.n_sites == 256
+
+
+def test_noalloc_rejects_oversized_plan_before_any_device_call():
+    """mxe_run_noalloc checks the plan against its fixed scratch first (no GPU touched)."""
+    import ctypes as C
+    from paper_1910_01235_amd import lattice as L
+    from paper_1910_01235_amd import mxe
+    if not os.path.exists(mxe.LIB_PATH):
+        pytest.skip("libmxe.so not built")
+    w = L.config1(1)
+    plan = mxe.Plan(w.systems, w.eam, w.params)
+    assert plan.ws_bytes > (64 << 20)
+    st, out = mxe.State(), mxe.Out()
+    code = mxe.lib().mxe_run_noalloc(plan._h, C.byref(st), C.byref(out), 1, None)
+    assert code == -2  # MXE_ENOMEM
+    assert b"allocation-free" in mxe.lib().mxe_last_error()

@@ -129,7 +129,10 @@ def test_relax_fp64_matches_oracle(mx):
     assert np.abs(dq).max() < 1e-10 * L.A0_CU
     assert rel_err(g["sigma"], sg, 1e-2) < 1e-10
     assert rel_err(g["mu"], info["mu"], 1e-2) < 1e-10
-    assert rel_err(g["force"], info["force"], 1e-2) < 1e-8
+    # relaxed forces are near ftol (1e-3 eV/A): normwise error with a 1e-2 eV/A floor
+    err_f = rel_err(g["force"], info["force"], 1e-2)
+    say(f"    relaxed force error {err_f:.2e}")
+    assert err_f < 1e-10
 
 
 def test_master_step_matches_oracle(mx):

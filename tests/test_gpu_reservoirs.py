@@ -85,7 +85,9 @@ def test_run_with_reservoirs_matches_oracle(mx, use_graph):
     assert rel_err(g["x"], r["x"], 1e-30) < 1e-10
     assert rel_err(g["sigma"], r["sigma"], 1e-30) < 1e-10
     assert sc[mx.S_TIME] == pytest.approx(r["t"], rel=1e-10)
-    assert sc[mx.S_RESERVOIR] == pytest.approx(r["uptake"][-1], rel=1e-9, abs=1e-13)
+    # the uptake is a sum over held sites of x changes: rounding floor n * 1e-14
+    say(f"    uptake {sc[mx.S_RESERVOIR]:.6e} vs oracle {r['uptake'][-1]:.6e}")
+    assert sc[mx.S_RESERVOIR] == pytest.approx(r["uptake"][-1], rel=1e-10, abs=1e-14 * s.n)
     x0 = s.x.copy()
     x0[res == O.RES_FIX_X] = res_val[res == O.RES_FIX_X]
     assert abs(sc[mx.S_SUMX] + sc[mx.S_RESERVOIR] - x0.sum()) < 1e-12 * x0.sum()
@@ -111,7 +113,9 @@ def test_held_layers_drive_a_steady_flux(mx):
     r = O.run(EAM, p, s.box, s.periodic, s.T, 3, s.q, s.sigma, s.x, s.type, res=res, res_val=res_val)
     g = gpu_arrays(plan, st, out)
     assert rel_err(g["x"], r["x"], 1e-30) < 1e-10
-    assert plan.scalars(out)[0, mx.S_RESERVOIR] == pytest.approx(r["uptake"][-1], rel=1e-9)
+    up = plan.scalars(out)[0, mx.S_RESERVOIR]
+    say(f"    uptake {up:.6e} vs oracle {r['uptake'][-1]:.6e}")
+    assert up == pytest.approx(r["uptake"][-1], rel=1e-10, abs=1e-14 * s.n)
 
 
 def test_reservoir_pointers_must_come_in_pairs(mx):
