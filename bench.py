@@ -38,6 +38,11 @@ OPS_PER_PAIR = 27 * 90
 # state, embedding terms, FIRE velocity and the six outputs.
 BYTES_FORCE_PER_PAIR = 2 * (14 * 8 + 8)
 BYTES_FORCE_PER_SITE = 8 + 8 + 1 + 8 * 3 + 8 * 4 + 8 * 6
+# Algorithmic HBM bytes of the density gather: each pair's (<f>, f0) and row entry
+# read from both ends and the neighbour's emission; per site its row count, x,
+# type and the five outputs (rho_bar, rho0, G, A~, B~) plus the packed record.
+BYTES_DENSITY_PER_PAIR = 2 * (16 + 8 + 8)
+BYTES_DENSITY_PER_SITE = 4 + 1 + 8 + 8 + 8 * 5 + 64
 # The timed runs bracket only the pair kernel with HIP events (every event
 # drains the queue); the per-family breakdown comes from this many further
 # steps with every family bracketed.
@@ -60,62 +65,153 @@ COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/cs
 
 def counter_traffic(family: str):
     """Scaled HBM bytes per launch of a kernel family, or None if the sources changed."""
+    if _sources_hash() != COUNTERS["sources_sha256_16"] or family not in COUNTERS:
+        return None
+    c = COUNTERS[family]
+    return (COUNTER_SCALE["fetch"] * c["fetch_kib"] + COUNTER_SCALE["write"] * c["write_kib"]) * 1024.0
+
+
+# VALU counters of the pair kernel per dispatch (summed over every shader
+# engine), from a rocprofv3 --pmc run of this bench (--steps 2 --warmup 1
+# --no-extras --no-cpu-baseline). SQ_INSTS_* count wave instructions;
+# VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
+# Valid only for the sources they were taken on.
+VALU_COUNTERS = dict(sources_sha256_16="", pair={})
+
+
+def _sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in COUNTER_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != COUNTERS["sources_sha256_16"] or family not in COUNTERS:
+    return h.hexdigest()[:16]
+
+
+def valu_counters(pair_avg_s: float):
+    """Measured VALU use of the pair kernel (counters) against this run's kernel
+    time, or None if the counters were taken on other sources."""
+    c = VALU_COUNTERS["pair"]
+    if not c or VALU_COUNTERS["sources_sha256_16"] != _sources_hash() or pair_avg_s <= 0:
         return None
-    c = COUNTERS[family]
-    return (COUNTER_SCALE["fetch"] * c["fetch_kib"] + COUNTER_SCALE["write"] * c["write_kib"]) * 1024.0
+    lane_ops = c["SQ_INSTS_VALU"] * 64.0
+    f64 = (c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_MUL_F64"] + c["SQ_INSTS_VALU_ADD_F64"] +
+           c["SQ_INSTS_VALU_TRANS_F64"]) * 64.0
+    return dict(VALUBusy_pct=c["VALUBusy"], VALUUtilization_pct=c.get("VALUUtilization"),
+                valu_lane_ops_per_s=lane_ops / pair_avg_s,
+                valu_issue_frac=lane_ops / pair_avg_s / (PEAK_FP64_TOPS * 1e12),
+                fp64_lane_ops_per_s=f64 / pair_avg_s,
+                fp64_issue_frac=f64 / pair_avg_s / (PEAK_FP64_TOPS * 1e12),
+                fp64_share_of_valu=f64 / lane_ops, source="rocprofv3 --pmc, per dispatch")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(workload, n_sample: int):
-    """The CPU oracle timed on a bounded sample of the same state."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload, n_sample: int, n_single: int, c0_oracle_s=None):
+    """The CPU oracle timed on bounded samples of the same state: one evaluation
+    of the first n_sample sites with OpenMP on every host thread, and of the first
+    n_single sites on one thread."""
     import numpy as np
 
     import oracle as O
     s = workload.systems[0]
-    n_sample = min(n_sample, s.n)
-    sel = np.arange(n_sample, dtype=np.int32)
     O.lib()
-    t0 = time.perf_counter()
-    O.evaluate_sites(workload.eam, s.box, s.periodic, s.T, s.q, s.sigma, s.x, s.type, sel)
-    dt = time.perf_counter() - t0
-    return dict(value=n_sample / dt, unit="site-evals/s", cores=O.num_threads(), kind="oracle",
-                sample=f"one evaluation (density pass over the sample and its neighbours, force/mu "
-                       f"pass over the sample) of the first {n_sample} of {s.n} sites of the "
-                       f"initial state; {dt:.2f} s wall")
+    cores = O.num_threads()
+
+    def rate(n):
+        sel = np.arange(min(n, s.n), dtype=np.int32)
+        t0 = time.perf_counter()
+        O.evaluate_sites(workload.eam, s.box, s.periodic, s.T, s.q, s.sigma, s.x, s.type, sel)
+        return len(sel), time.perf_counter() - t0
+
+    n_all, dt_all = rate(n_sample)
+    O.set_num_threads(1)
+    try:
+        n_one, dt_one = rate(n_single)
+    finally:
+        O.set_num_threads(cores)
+    out = dict(value=n_all / dt_all, unit="site-evals/s", cores=cores, kind="oracle",
+               sample=f"one evaluation (density pass over the sample and its neighbours, force/mu "
+                      f"pass over the sample) of the first {n_all} of {s.n} sites of the "
+                      f"initial state; {dt_all:.2f} s wall on {cores} threads",
+               cpu_model=cpu_model(), nproc=os.cpu_count(),
+               single_thread=dict(value=n_one / dt_one, unit="site-evals/s", cores=1,
+                                  sample=f"first {n_one} sites, {dt_one:.2f} s wall"))
+    if c0_oracle_s is not None:
+        out["c0_full_run_s"] = c0_oracle_s
+        out["c0_full_run_cores"] = cores
+    return out
 
 
-def batched_legs(n_requests: int, n_steps: int, seed: int = 4):
-    """Many independent systems: one batched plan, one at a time, and served.
-
-    Requests: cubic vacancy or alloy systems, sizes log-uniform in [500, 50,000]
-    sites, T in [600, 1200] K. Rates count site-evaluations (sites x
-    evaluations) and systems completed per second of wall time."""
+def sampled_errors(workload, plan, st, out, ws, precision, n_sample=64, seed=0):
+    """One evaluation at the current GPU state, compared with the oracle on
+    sampled sites (normwise relative errors, the tests' floors)."""
     import numpy as np
     import torch
 
+    import oracle as O
+    s = workload.systems[0]
+    plan.evaluate(st, out, ws)
+    torch.cuda.synchronize()
+    q = torch.stack([st.qx, st.qy, st.qz], 1).cpu().numpy()
+    sg, x = st.sigma.cpu().numpy(), st.x.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(s.n, min(n_sample, s.n), replace=False)).astype(np.int32)
+    eam = dict(workload.eam, quad_rule=int(plan.params.quad_rule))
+    o = O.evaluate_sites(eam, s.box, s.periodic, s.T, q, sg, x, s.type, sel)
+    f = torch.stack([out.fx, out.fy, out.fz, out.fsigma], 1).cpu().numpy()[sel]
+
+    def rel(a, b, floor):
+        return float(np.abs(a - b).max() / max(np.abs(b).max(), floor))
+    return dict(sites=len(sel), force=rel(f, o["force"], 1e-2),
+                mu=rel(out.mu.cpu().numpy()[sel], o["mu"], 1e-2),
+                rho_bar=rel(out.rho_bar.cpu().numpy()[sel], o["rho_bar"], 1.0),
+                e_site=rel(out.e_site.cpu().numpy()[sel], o["e_site"], 1e-2),
+                bar=1e-10 if precision == "fp64" else 1e-5)
+
+
+def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
+                  budget_gb: float = 24.0):
+    """The serving workload: independent systems run as one batched plan, one at
+    a time, and served with continuous batching at Poisson arrival rates given as
+    multiples of the batched capacity.
+
+    Requests: cubic vacancy or alloy systems, sizes log-uniform in [500, 50,000]
+    sites, T in [600, 1200] K, each for n_steps diffusion steps of <= 50 FIRE
+    updates. Latency = completion - arrival. The one-at-a-time path is measured
+    once (every request alone, back to back); its latencies under each arrival
+    stream follow from the measured service times of a first-come-first-served
+    single server."""
+    import numpy as np
+    import torch
+
+    from paper_1910_01235_amd import autotune
     from paper_1910_01235_amd import lattice as L
     from paper_1910_01235_amd import mxe
     from paper_1910_01235_amd import serve
 
     systems = L.config4_requests(seed=seed, n_requests=n_requests)
-    params = dict(L.DEFAULT_PARAMS)
     n_tot = sum(s.n for s in systems)
-    reqs = serve.poisson_requests(systems, n_steps=n_steps, rate=0.0)
+    base = dict(L.DEFAULT_PARAMS)
+    # launch shapes from the project's autotuner, on this batch
+    params, tuned = autotune.tuned_params(systems, L.DEFAULT_EAM, base, cache=None, reps=2)
+    shapes = {k: tuned[k] for k in ("gather_lanes", "force_lanes", "pair_block")}
+    log(f"serving: {len(systems)} requests, {n_tot} sites, tuned shapes {shapes}")
 
-    # one at a time: a plan per request, in order (the plain path)
-    torch.cuda.synchronize()
-    _, one = serve.serve_one_at_a_time(L.DEFAULT_EAM, params, reqs, realtime=False)
-
-    # all requests in one batched plan
+    # all requests in one batched plan: the capacity
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = mxe.Plan(systems, L.DEFAULT_EAM, params)
@@ -129,30 +225,61 @@ def batched_legs(n_requests: int, n_steps: int, seed: int = 4):
     status_b = int(np.bitwise_or.reduce(sc[:, mxe.S_STATUS].astype(np.int64)))
     del plan, st, out, ws
     torch.cuda.empty_cache()
-    batched = dict(systems_per_s=len(systems) / wall_b, site_evals_per_s=site_evals / wall_b,
-                   wall_s=wall_b, status=status_b)
+    cap = len(systems) / wall_b
+    batched = dict(systems_per_s=cap, site_evals_per_s=site_evals / wall_b,
+                   site_steps_per_s=n_tot * n_steps / wall_b, wall_s=wall_b,
+                   evals_per_system_step=float(evals_b.mean() / n_steps), status=status_b)
+    log(f"serving: batched {wall_b:.1f} s, {cap:.1f} systems/s")
 
-    # served: Poisson arrivals at 0.8 x the batched capacity, continuous batching
+    # one at a time: a plan per request, back to back (the plain path)
+    reqs0 = serve.poisson_requests(systems, n_steps=n_steps, rate=0.0)
+    res1, one = serve.serve_one_at_a_time(
+        L.DEFAULT_EAM, params, reqs0, realtime=False,
+        progress=lambda k: log(f"serving: one at a time, {k} done") if k % 64 == 0 else None)
+    service = {r.rid: r.completed - r.admitted for r in res1}
+    log(f"serving: one at a time {one['makespan_s']:.1f} s")
+
+    def fcfs(reqs):
+        """Latencies of a first-come-first-served single server with these service times."""
+        c, lat = 0.0, []
+        for r in sorted(reqs, key=lambda r: (r.arrival, r.rid)):
+            c = max(c, r.arrival) + service[r.rid]
+            lat.append(c - r.arrival)
+        lat = np.array(lat)
+        return dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                    systems_per_s=len(lat) / c)
+
+    # served: continuous batching over a slot pool sized to the HBM budget
     per_site = serve.bytes_per_site(L.DEFAULT_EAM, params)
-    caps = serve.pool_capacities(24e9, per_site)
+    caps = serve.pool_capacities(budget_gb * 1e9, per_site)
     srv = serve.Server(L.DEFAULT_EAM, params, caps)
     warm = serve.poisson_requests([L.vacancy_bulk(5, 1, 800.0, 0)], n_steps=1, rate=0.0)
     srv.serve(warm, realtime=False)  # records the step graph
-    rate = 0.8 * batched["systems_per_s"]
-    reqs_p = serve.poisson_requests(systems, n_steps=n_steps, rate=rate, seed=seed)
-    res, rejected, st_s = srv.serve(reqs_p, realtime=True)
-    served = dict(arrival_rate_per_s=rate, systems_per_s=st_s["systems_per_s"],
-                  site_steps_per_s=st_s["site_steps_per_s"], p50_s=st_s["p50_s"], p99_s=st_s["p99_s"],
-                  rejected=len(rejected), slots=st_s["slots"], footprint_gb=st_s["footprint_bytes"] / 1e9,
-                  status=int(np.bitwise_or.reduce([r.status for r in res])) if res else 0)
+    served = []
+    for f in rate_factors:
+        rate = f * cap
+        reqs = serve.poisson_requests(systems, n_steps=n_steps, rate=rate, seed=seed)
+        res, rejected, st_s = srv.serve(
+            reqs, realtime=True,
+            progress=lambda k: log(f"serving: rate {f}, {k} done") if k % 64 == 0 else None)
+        served.append(dict(
+            rate_factor=f, arrival_rate_per_s=rate, systems_per_s=st_s["systems_per_s"],
+            site_steps_per_s=st_s["site_steps_per_s"], p50_s=st_s["p50_s"], p99_s=st_s["p99_s"],
+            makespan_s=st_s["makespan_s"], gpu_steps=st_s["gpu_steps"], rejected=len(rejected),
+            status=int(np.bitwise_or.reduce([r.status for r in res])) if res else 0,
+            one_at_a_time=fcfs(reqs)))
+        log(f"serving: rate {f} x capacity: {st_s['systems_per_s']:.1f} systems/s, "
+            f"p50 {st_s['p50_s']:.2f} s, p99 {st_s['p99_s']:.2f} s")
+    out = dict(requests=len(systems), sites=n_tot, steps_per_request=n_steps,
+               max_relax=params["max_relax"], shapes=shapes, batched=batched,
+               one_at_a_time=dict(systems_per_s=one["systems_per_s"], makespan_s=one["makespan_s"],
+                                  p50_s=one["p50_s"], p99_s=one["p99_s"],
+                                  arrivals="all at t = 0"),
+               batched_vs_one_at_a_time=cap / one["systems_per_s"],
+               served=served, slots=len(caps), footprint_gb=srv.footprint_bytes / 1e9)
     del srv
     torch.cuda.empty_cache()
-    return dict(requests=len(systems), sites=n_tot, steps_per_request=n_steps,
-                max_relax=params["max_relax"], batched=batched,
-                one_at_a_time=dict(systems_per_s=one["systems_per_s"], makespan_s=one["makespan_s"],
-                                   p50_s=one["p50_s"], p99_s=one["p99_s"]),
-                batched_vs_one_at_a_time=batched["systems_per_s"] / one["systems_per_s"],
-                served=served)
+    return out
 
 
 def timed_run(plan, st, out, ws, steps, use_graph, profile):
@@ -173,16 +300,94 @@ def timed_run(plan, st, out, ws, steps, use_graph, profile):
     return wall, sc, prof
 
 
+def fullsize_leg(w, precision, steps, warmup, quad_rule=0):
+    """A large workload at its full size: `warmup` untimed and `steps` timed
+    diffusion steps (eager, HIP events around the pair kernel), a breakdown of
+    every kernel family over one more step, and errors against the oracle on
+    sampled sites of an evaluation at the final state."""
+    import torch
+
+    from paper_1910_01235_amd import mxe
+    s = w.systems[0]
+    eam = dict(w.eam, quad_rule=quad_rule)
+    plan = mxe.Plan([s], eam, w.params, precision=precision)
+    st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+    plan.run(st, out, ws, warmup, use_graph=True)
+    wall, sc, prof = timed_run(plan, st, out, ws, steps, use_graph=False, profile="pair")
+    ev = int(sc[mxe.S_TOTAL_EVALS])
+    _, _, prof_b = timed_run(plan, st, out, ws, 1, use_graph=False, profile=True)
+    n_mobile = int((s.type != 3).sum())
+    res = dict(workload=w.name, sites=s.n, precision=precision, value=s.n * ev / wall,
+               unit="site-evals/s", site_steps_per_s=n_mobile * steps / wall,
+               ms_per_step=wall / steps * 1e3, steps=steps, evals=ev,
+               pairs_per_eval=float(sc[mxe.S_PAIR_EVALS]) / max(ev, 1),
+               list_builds=int(sc[mxe.S_REBUILDS]), status=int(sc[mxe.S_STATUS]),
+               pair_ms_avg=prof["pair"][0] / max(prof["pair"][1], 1),
+               kernel_ms_avg={k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof_b.items()})
+    res["error_vs_oracle"] = sampled_errors(w, plan, st, out, ws, precision)
+    del st, out, ws, plan
+    torch.cuda.empty_cache()
+    return res
+
+
+def c0_leg():
+    """The plain-method workload end to end: 256 sites, 20 diffusion steps of up
+    to 50 FIRE updates, one graph replay per step, against the oracle's run."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_1910_01235_amd import lattice as L
+    from paper_1910_01235_amd import mxe
+    w = L.config0(0)
+    s = w.systems[0]
+    plan = mxe.Plan([s], w.eam, w.params)
+    st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+    plan.run(st, out, ws, 1, use_graph=True)  # records the graph on these buffers
+    torch.cuda.synchronize()
+    st0 = plan.state([s])  # back to the initial state, same buffers
+    for name in ("qx", "qy", "qz", "sigma", "x"):
+        getattr(st, name).copy_(getattr(st0, name))
+    out.scalars.zero_()
+    wall, sc, _ = timed_run(plan, st, out, ws, w.n_steps, use_graph=True, profile=False)
+    ev = int(sc[mxe.S_TOTAL_EVALS])
+    t0 = time.perf_counter()
+    r = O.run(w.eam, w.params, s.box, s.periodic, s.T, w.n_steps, s.q, s.sigma, s.x, s.type)
+    t_or = time.perf_counter() - t0
+    x = st.x.cpu().numpy()
+    q = torch.stack([st.qx, st.qy, st.qz], 1).cpu().numpy()
+    dq = q - r["q"]
+    dq -= np.array(s.box) * np.round(dq / np.array(s.box))
+    err = dict(dx=float(np.abs((x - s.x) - (r["x"] - s.x)).max() / np.abs(r["x"] - s.x).max()),
+               q_abs=float(np.abs(dq).max()),
+               mu=float(np.abs(out.mu.cpu().numpy() - r["mu"]).max() / np.abs(r["mu"]).max()),
+               time=abs(float(sc[mxe.S_TIME]) - r["t"]) / r["t"],
+               updates_last_step=[int(sc[mxe.S_UPDATES]), int(r["updates"][-1])], bar=1e-10)
+    return dict(workload=w.name, sites=s.n, steps=w.n_steps, max_relax=w.params["max_relax"],
+                wall_s=wall, value=s.n * ev / wall, unit="site-evals/s", evals=ev,
+                site_steps_per_s=s.n * w.n_steps / wall, ms_per_step=wall / w.n_steps * 1e3,
+                launch="one graph replay per diffusion step", status=int(sc[mxe.S_STATUS]),
+                oracle_wall_s=t_or, oracle_threads=O.num_threads(), error_vs_oracle=err)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=256000)
+    ap.add_argument("--cpu-single-sample", type=int, default=16000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the graph, FP32 and batched legs")
-    ap.add_argument("--batch-requests", type=int, default=64)
-    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline leg (no other legs, no oracle errors)")
+    ap.add_argument("--legs", default="graph,fp32,degree3,variants,c0,c2,c3,serving",
+                    help="comma-separated extra legs")
+    ap.add_argument("--fullsize-steps", type=int, default=3,
+                    help="timed diffusion steps of the slab and nanowire legs")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-steps", type=int, default=50)
+    ap.add_argument("--serve-rates", default="0.25,0.5,0.8,1.0,2.0",
+                    help="arrival rates as multiples of the batched capacity")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -190,6 +395,7 @@ def main():
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               "(the library has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
+    legs = set() if args.no_extras else set(x for x in args.legs.split(",") if x)
 
     import numpy as np
     import torch
@@ -233,8 +439,13 @@ def main():
     pair_avg_s = pair_ms / max(pair_launches, 1) / 1e3
     roof_pair = dict(bound="alu", achieved=ops / pair_avg_s / 1e12 if pair_avg_s > 0 else 0.0,
                      peak=PEAK_FP64_TOPS, unit="Tops/s", kernel="k_pair<double>",
-                     traffic=counter_traffic("pair"), traffic_unit="B/launch")
+                     traffic=counter_traffic("pair"), traffic_unit="B/launch",
+                     work="algorithmic: 27 nodes x 90 FP64 operations per listed pair "
+                          "(nominal count, not the executed instructions)")
     roof_pair["frac"] = roof_pair["achieved"] / roof_pair["peak"]
+    valu = valu_counters(pair_avg_s)
+    if valu is not None:
+        roof_pair["valu_counters"] = valu
     evals_per_launch = evals_b / max(fam["force"]["launches"], 1)
     bytes_force = (BYTES_FORCE_PER_PAIR * pair_evals_b / max(evals_b, 1) + BYTES_FORCE_PER_SITE * n) \
         * evals_per_launch
@@ -242,8 +453,18 @@ def main():
     roof_force = dict(bound="hbm", achieved=bytes_force / force_avg_s / 1e9 if force_avg_s > 0 else 0.0,
                       peak=PEAK_HBM_GBS, unit="GB/s", kernel="k_force<double> + k_force_fold",
                       traffic=counter_traffic("force"), traffic_unit="B/launch",
-                      algorithmic_bytes=bytes_force)
+                      algorithmic_bytes=bytes_force,
+                      work="each pair's 14 moments and row entry read from both ends, plus "
+                           "per-site state, embedding terms and outputs")
     roof_force["frac"] = roof_force["achieved"] / roof_force["peak"]
+    bytes_dens = (BYTES_DENSITY_PER_PAIR * pair_evals_b / max(evals_b, 1) + BYTES_DENSITY_PER_SITE * n) \
+        * evals_b / max(fam["density"]["launches"], 1)
+    dens_avg_s = fam["density"]["ms_avg"] / 1e3
+    roof_dens = dict(bound="hbm", achieved=bytes_dens / dens_avg_s / 1e9 if dens_avg_s > 0 else 0.0,
+                     peak=PEAK_HBM_GBS, unit="GB/s", kernel="k_density<double>",
+                     traffic=counter_traffic("density"), traffic_unit="B/launch",
+                     algorithmic_bytes=bytes_dens)
+    roof_dens["frac"] = roof_dens["achieved"] / roof_dens["peak"]
     dominant = max(fam, key=lambda k: fam[k]["ms_total"])
     roofline = roof_pair if dominant != "force" else roof_force
 
@@ -269,51 +490,33 @@ def main():
         "pairs_per_eval": pair_evals / max(evals, 1),
         "status": status,
         "roofline": roofline,
-        "roofline_all": {"pair": roof_pair, "force": roof_force},
+        "roofline_all": {"pair": roof_pair, "force": roof_force, "density": roof_dens},
         "pair_ms_avg_timed": pair_ms / max(pair_launches, 1),
         "kernel_ms": fam,
         "kernel_ms_from": f"{BREAKDOWN_STEPS} steps after the timed region, every family bracketed",
         "dominant_kernel": dominant,
     }
+    if legs:
+        result["error_vs_oracle"] = sampled_errors(w, plan, st, out, ws, "fp64")
 
-    if not args.no_extras:
+    if "graph" in legs:
         wall_g, sc_g, _ = timed_run(plan, st, out, ws, args.steps, use_graph=True, profile=False)
         result["graph"] = dict(value=n * int(sc_g[mxe.S_TOTAL_EVALS]) / wall_g,
                                ms_per_step=wall_g / args.steps * 1e3,
                                evals=int(sc_g[mxe.S_TOTAL_EVALS]))
         log(f"graph leg: {wall_g:.3f} s")
-        del st, out, ws, plan
-        torch.cuda.empty_cache()
-        p32 = mxe.Plan([s], w.eam, w.params, precision="fp32")
-        st32, out32, ws32 = p32.state([s]), p32.out(), p32.workspace()
-        p32.run(st32, out32, ws32, args.warmup, use_graph=True)
-        wall_32, sc_32, _ = timed_run(p32, st32, out32, ws32, args.steps, use_graph=False,
-                                      profile="pair")
-        ev32 = int(sc_32[mxe.S_TOTAL_EVALS])
-        _, _, prof32 = timed_run(p32, st32, out32, ws32, BREAKDOWN_STEPS, use_graph=False, profile=True)
-        result["fp32_mixed"] = dict(value=n * ev32 / wall_32, ms_per_step=wall_32 / args.steps * 1e3,
-                                    evals=ev32, status=int(sc_32[mxe.S_STATUS]),
-                                    kernel_ms={k: v[0] for k, v in prof32.items()})
-        log(f"fp32 leg: {wall_32:.3f} s")
-        del st32, out32, ws32, p32
-        torch.cuda.empty_cache()
+    del st, out, ws, plan
+    torch.cuda.empty_cache()
+    if "fp32" in legs:
+        result["fp32_mixed"] = fullsize_leg(w, "fp32", args.steps, args.warmup)
+        log(f"fp32 leg: {result['fp32_mixed']['value']:.4g} site-evals/s")
+    if "degree3" in legs:
         # the paper's own degree-3 rule (12 nodes in the pair's 6-D space)
         result["degree3"] = {}
         for prec in ("fp64", "fp32"):
-            eam3 = dict(w.eam, quad_rule=1)
-            p3 = mxe.Plan([s], eam3, w.params, precision=prec)
-            st3, out3, ws3 = p3.state([s]), p3.out(), p3.workspace()
-            p3.run(st3, out3, ws3, args.warmup, use_graph=True)
-            wall3, sc3, _ = timed_run(p3, st3, out3, ws3, args.steps, use_graph=False, profile="pair")
-            ev3 = int(sc3[mxe.S_TOTAL_EVALS])
-            _, _, prof3 = timed_run(p3, st3, out3, ws3, BREAKDOWN_STEPS, use_graph=False, profile=True)
-            result["degree3"][prec] = dict(
-                value=n * ev3 / wall3, ms_per_step=wall3 / args.steps * 1e3, evals=ev3,
-                status=int(sc3[mxe.S_STATUS]),
-                kernel_ms_avg={k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof3.items()})
-            log(f"degree-3 {prec} leg: {wall3:.3f} s")
-            del st3, out3, ws3, p3
-            torch.cuda.empty_cache()
+            result["degree3"][prec] = fullsize_leg(w, prec, args.steps, args.warmup, quad_rule=1)
+            log(f"degree-3 {prec} leg: {result['degree3'][prec]['value']:.4g} site-evals/s")
+    if "variants" in legs:
         # state variants on the same workload: site temperatures, reservoir sites
         result["variants"] = {}
         rng = np.random.default_rng(3)
@@ -341,9 +544,23 @@ def main():
             log(f"{name} leg: {wall_v:.3f} s")
             del stv, outv, wsv, pv
             torch.cuda.empty_cache()
+    c0_oracle_s = None
+    if "c0" in legs:
+        result["c0_full_run"] = c0_leg()
+        c0_oracle_s = result["c0_full_run"]["oracle_wall_s"]
+        log(f"plain-method full run: {result['c0_full_run']['wall_s']:.3f} s on the GPU, "
+            f"{c0_oracle_s:.1f} s for the oracle")
+    if "c2" in legs:
+        result["c2_alloy_slab_131k"] = fullsize_leg(L.config2(2), "fp32", args.fullsize_steps, 1)
+        log(f"alloy slab leg: {result['c2_alloy_slab_131k']['value']:.4g} site-evals/s")
+    if "c3" in legs:
+        result["c3_nanowire_265k"] = fullsize_leg(L.config3(3), "fp32", args.fullsize_steps, 1)
+        log(f"nanowire leg: {result['c3_nanowire_265k']['value']:.4g} site-evals/s")
+    if "serving" in legs:
         t0 = time.perf_counter()
-        result["many_systems"] = batched_legs(args.batch_requests, args.batch_steps)
-        log(f"batched/served legs: {time.perf_counter() - t0:.1f} s")
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        result["serving"] = serving_sweep(args.serve_requests, args.serve_steps, rates)
+        log(f"serving legs: {time.perf_counter() - t0:.1f} s")
 
     if args.calib_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -355,7 +572,7 @@ def main():
         result["calib_copy_bytes"] = a.numel() * 8
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_single_sample, c0_oracle_s)
     print(json.dumps(result), flush=True)
 
 

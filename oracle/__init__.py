@@ -70,6 +70,7 @@ def lib():
             build()
         _lib = C.CDLL(_LIB_PATH)
         _lib.oref_num_threads.restype = C.c_int
+        _lib.oref_set_num_threads.argtypes = [C.c_int]
     return _lib
 
 
@@ -136,6 +137,11 @@ def make_params(p: dict) -> _Params:
 
 def num_threads() -> int:
     return lib().oref_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops (CPU-baseline timing)."""
+    lib().oref_set_num_threads(int(n))
 
 
 def quadrature():

@@ -41,6 +41,15 @@ int oref_num_threads(void) {
 #endif
 }
 
+/* threads of later parallel loops (timing of the CPU baseline only) */
+void oref_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Occupancy model (Sec. 2, Eq. occupancy; App. B.2.1).                      */
 /* Each site holds species sp1 with probability p1 and species sp0 with      */

@@ -72,6 +72,7 @@ typedef struct {
 #define OREF_ERANGE (-5)
 
 int oref_num_threads(void);
+void oref_set_num_threads(int n);
 
 /* 27-node product Gauss-Hermite rule for a standard 3-D normal variable. */
 void oref_quadrature(double zeta[27][3], double w[27]);

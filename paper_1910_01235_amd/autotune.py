@@ -89,7 +89,7 @@ def tune(systems, eam: dict, params: dict, precision: str = "fp64", reps: int = 
 def tuned_params(systems, eam: dict, params: dict, precision: str = "fp64", cache: Cache = None,
                  retune: bool = False, reps: int = 5):
     """params with the tuned launch shapes (tuned now, or taken from the cache)."""
-    key = bucket(systems, precision, int(eam.get("quad_rule", 0)))
+    key = bucket(systems, precision, int(params.get("quad_rule", eam.get("quad_rule", 0))))
     hit = None if (cache is None or retune) else cache.get(key)
     if hit is not None and "force_lanes" not in hit:
         hit = None  # written before the force gather had a shape of its own

@@ -173,8 +173,9 @@ class Server:
     def step(self):
         self.plan.run(self.st, self.out, self.ws, 1, use_graph=True)
 
-    def serve(self, requests: list, realtime: bool = True):
-        """Serve a request stream; returns (results, rejected ids, stats)."""
+    def serve(self, requests: list, realtime: bool = True, progress=None):
+        """Serve a request stream; returns (results, rejected ids, stats).
+        progress: optional callable, given the number of results after each completion."""
         torch = self.torch
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         n_steps_of = {r.rid: r.n_steps for r in pending}
@@ -222,6 +223,8 @@ class Server:
                 x, q, sg, tsim, st = self.collect(slot, r.system.n)
                 results.append(Result(r.rid, r.system.n, slot, r.arrival, ta, tc, x, q, sg, tsim, st))
                 self.retire(slot)
+                if progress is not None:
+                    progress(len(results))
         makespan = now()
         lat = np.array([r.latency for r in results]) if results else np.zeros(1)
         stats = dict(systems=len(results), rejected=len(rejected), makespan_s=makespan,
@@ -235,8 +238,9 @@ class Server:
 
 
 def serve_one_at_a_time(eam: dict, params: dict, requests: list, precision: str = "fp64",
-                        realtime: bool = True, device: str = "cuda"):
-    """The plain path: each request alone on its own plan, in arrival order."""
+                        realtime: bool = True, device: str = "cuda", progress=None):
+    """The plain path: each request alone on its own plan, in arrival order.
+    progress: optional callable, given the number of requests done after each."""
     import torch
     results = []
     pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -256,6 +260,8 @@ def serve_one_at_a_time(eam: dict, params: dict, requests: list, precision: str 
         results.append(Result(r.rid, r.system.n, 0, r.arrival, ta, tc, st.x.cpu().numpy(), q,
                               st.sigma.cpu().numpy(), float(sc[mxe.S_TIME]), int(sc[mxe.S_STATUS])))
         del plan, st, out, ws
+        if progress is not None:
+            progress(len(results))
     makespan = now()
     lat = np.array([r.latency for r in results]) if results else np.zeros(1)
     stats = dict(systems=len(results), makespan_s=makespan,
