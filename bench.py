@@ -176,7 +176,12 @@ def sampled_errors(workload, plan, st, out, ws, precision, n_sample=64, seed=0):
 
     def rel(a, b, floor):
         return float(np.abs(a - b).max() / max(np.abs(b).max(), floor))
-    return dict(sites=len(sel), force=rel(f, o["force"], 1e-2),
+    # FP32 moments round each pair's force terms (about 1 eV/A in the first
+    # shell) to 6e-8 relative; a relaxed site's net force is what is left after
+    # they cancel, so the FP32 force error is measured against that scale
+    f_floor = 1e-2 if precision == "fp64" else 1.0
+    return dict(sites=len(sel), force=rel(f, o["force"], f_floor), force_floor_eV_A=f_floor,
+                force_floor_1e_2=rel(f, o["force"], 1e-2), force_max=float(np.abs(o["force"]).max()),
                 mu=rel(out.mu.cpu().numpy()[sel], o["mu"], 1e-2),
                 rho_bar=rel(out.rho_bar.cpu().numpy()[sel], o["rho_bar"], 1.0),
                 e_site=rel(out.e_site.cpu().numpy()[sel], o["e_site"], 1e-2),

@@ -323,9 +323,12 @@ mxe_status mxe_run_noalloc(mxe_plan* plan, const mxe_state* state, const mxe_out
  * Sec. 3.1). Items, each a dense int32 array at a byte offset in the workspace:
  *   MXE_L_NBR         [n_sites][k_max]: row i lists the neighbours j of site i
  *                     (ascending; the first count[i] entries are valid): every
- *                     pair with |rbar_ij| < r_c + 3 s_ij + skin at the last build
- *                     (s_ij = sqrt(sigma_i^2 + sigma_j^2)), interstitial pairs
- *                     excluded, plus possibly pairs within 1e-5 A of that radius
+ *                     pair with |rbar_ij| < r_c + reach_ij + skin at the last
+ *                     build, reach_ij = 3 sqrt(sigma_i^2 + sigma_j^2) under the
+ *                     27-node rule and sqrt(6) max(sigma_i, sigma_j) under the
+ *                     degree-3 rule (the rule's farthest node), interstitial
+ *                     pairs excluded, plus possibly pairs within 1e-5 A of that
+ *                     radius
  *   MXE_L_NBR_COUNT   [n_sites]
  *   MXE_L_BOND        [n_sites][bond_max]: bonds of mobile site i (ascending),
  *                     same-type sites closer than r_bond

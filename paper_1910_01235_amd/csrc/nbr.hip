@@ -1,13 +1,15 @@
 // Neighbour lists, pair lists and nearest-neighbour bonds (cell binning).
 //
 // A pair interacts only if some quadrature node lies inside r_c, which needs
-// |rbar| < r_c + 3 s (the farthest node of the rule sits 3 s from the mean).
-// The list holds every pair with |rbar| < r_c + 3 s_build + skin, where s_build
-// uses both widths at the time of the build. The pair stays listed while
+// |rbar| < r_c + reach: the farthest node of the 27-node product rule sits
+// 3 s from the mean, that of the degree-3 rule sqrt(6) max(sigma_i, sigma_j).
+// The list holds every pair with |rbar| < r_c + reach_build + skin, where
+// reach_build uses both widths at the time of the build. The pair stays listed while
 // 2 max|dq| + 3 sqrt(2) max(sigma - sigma_build, 0) <= skin over the system's
 // sites, since |rbar| loses at most |dq_i| + |dq_j| and
-// s <= s_build + sqrt(2) max(sigma - sigma_build, 0). The FIRE update records both
-// maxima; the build runs when their sum leaves the skin. Cells are as wide as the
+// s <= s_build + sqrt(2) max(sigma - sigma_build, 0) (the degree-3 reach grows by
+// less: sqrt(6) < 3 sqrt(2)). The FIRE update records both maxima; the build
+// runs when their sum leaves the skin. Cells are as wide as the
 // largest radius allowed by sigma_cap.
 //
 // Build chain per system (each kernel skips systems whose rebuild flag is 0):
@@ -346,6 +348,7 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
         const int T = st_pre[27];
         const int ntiles = (T + kCellTile - 1) / kCellTile;
         const double reach = m.r_c + m.skin + 1e-6;
+        const bool d3 = m.quad_rule == MXE_QUAD_DEGREE3;
         const double ib0 = 1.0 / S.box[0], ib1 = 1.0 / S.box[1], ib2 = 1.0 / S.box[2];
         // minimum image: periodic axes subtract box * rint(d / box), open axes nothing
         const double pb0 = S.periodic[0] ? S.box[0] : 0.0, pb1 = S.periodic[1] ? S.box[1] : 0.0,
@@ -395,6 +398,7 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
             const bool has = k < nsite;
             int i = 0, ti = 0;
             double qi0 = 0.0, qi1 = 0.0, qi2 = 0.0, si2 = 0.0;
+            float sig_i = 0.0f;
             if (has) {
                 int jt;
                 double4 ri;
@@ -412,6 +416,7 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
                 qi1 = ri.y;
                 qi2 = ri.z;
                 si2 = ri.w * ri.w;
+                sig_i = (float)ri.w;
             }
             // bonds of a mobile site: same-type sites closer than r_bond, by the
             // exact FP64 distance (minimum image by division)
@@ -436,8 +441,11 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
                     dx -= pb0 * rint(dx * ib0);
                     dy -= pb1 * rint(dy * ib1);
                     dz -= pb2 * rint(dz * ib2);
-                    const float sf = __builtin_sqrtf((float)(si2 + rj.w * rj.w));
-                    const double rl = reach + 3.0 * (double)sf;
+                    // the rule's farthest node from the mean: 3 s under the product
+                    // rule, sqrt(6) max(sigma_i, sigma_j) under the degree-3 rule
+                    const double rl =
+                        reach + (d3 ? 2.449489742783178 * (double)fmaxf(sig_i, (float)rj.w)
+                                    : 3.0 * (double)__builtin_sqrtf((float)(si2 + rj.w * rj.w)));
                     const bool ok = in & (j != i) & (pair_cls(ti, jt & 3) >= 0) &
                                     (dx * dx + dy * dy + dz * dz < rl * rl);
                     const unsigned long long mask = __ballot(ok);

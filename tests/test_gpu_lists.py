@@ -36,17 +36,20 @@ def mx():
 
 def _cases():
     w1 = L.config1(1)
-    yield "c1_vacancy_256k", w1.systems[0], w1
-    yield "c1_jittered", L.jitter(w1.systems[0], 11, dq=0.05, sig=(0.07, 0.13)), w1
+    yield "c1_vacancy_256k", w1.systems[0], w1, 0
+    yield "c1_jittered", L.jitter(w1.systems[0], 11, dq=0.05, sig=(0.07, 0.13)), w1, 0
+    yield "c1_jittered_degree3", L.jitter(w1.systems[0], 12, dq=0.05, sig=(0.07, 0.13)), w1, 1
     w3 = L.config3(3)
-    yield "c3_nanowire_265k", w3.systems[0], w3
+    yield "c3_nanowire_265k", w3.systems[0], w3, 0
 
 
-@pytest.mark.parametrize("name,s,w", list(_cases()), ids=lambda v: v if isinstance(v, str) else "")
-def test_lists_and_bonds_match_oracle(mx, name, s, w):
+@pytest.mark.parametrize("name,s,w,rule", list(_cases()), ids=lambda v: v if isinstance(v, str) else "")
+def test_lists_and_bonds_match_oracle(mx, name, s, w, rule):
+    """The list radius is r_c + skin + the rule's farthest node from the mean:
+    3 s_ij (27-node product rule) or sqrt(6) max(sigma_i, sigma_j) (degree-3)."""
     p = w.params
     say(f"[gpu] lists of {name}: {s.n} sites")
-    plan = mx.Plan([s], w.eam, p)
+    plan = mx.Plan([s], dict(w.eam, quad_rule=rule), p)
     st, out, ws = plan.state([s]), plan.out(), plan.workspace()
     plan.run(st, out, ws, 0, use_graph=False)  # builds lists and bonds, runs no step
     torch.cuda.synchronize()
@@ -84,7 +87,10 @@ def test_lists_and_bonds_match_oracle(mx, name, s, w):
     per = np.array(s.periodic, dtype=float)
     d -= per * box * np.round(d / box)
     r = np.sqrt((d * d).sum(1))
-    R = r_list + 3.0 * np.sqrt(s.sigma[oi] ** 2 + s.sigma[oj] ** 2)
+    if rule == 0:
+        R = r_list + 3.0 * np.sqrt(s.sigma[oi] ** 2 + s.sigma[oj] ** 2)
+    else:
+        R = r_list + np.sqrt(6.0) * np.maximum(s.sigma[oi], s.sigma[oj])
     ii = (s.type[oi] == L.INTERSTITIAL) & (s.type[oj] == L.INTERSTITIAL)
     must = (r < R - BAND) & ~ii
     allowed = (r < R + BAND) & ~ii
