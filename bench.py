@@ -305,24 +305,39 @@ def timed_run(plan, st, out, ws, steps, use_graph, profile):
     return wall, sc, prof
 
 
-def fullsize_leg(w, precision, steps, warmup, quad_rule=0):
+def tuned(w, precision, params=None):
+    """The workload's parameters with the autotuner's launch shapes (tuned on this
+    GPU, or read from the tuner's cache) and the shapes chosen."""
+    from paper_1910_01235_amd import autotune
+    p, hit = autotune.tuned_params(w.systems, w.eam, params or w.params, precision=precision,
+                                   cache=autotune.Cache(), reps=3)
+    return p, {k: hit[k] for k in ("gather_lanes", "force_lanes", "pair_block", "gather_stride")}
+
+
+def fullsize_leg(w, precision, steps, warmup, quad_rule=0, params=None):
     """A large workload at its full size: `warmup` untimed and `steps` timed
     diffusion steps (eager, HIP events around the pair kernel), a breakdown of
     every kernel family over one more step, and errors against the oracle on
-    sampled sites of an evaluation at the final state."""
+    sampled sites of an evaluation at the final state. params: the workload's
+    parameters with launch shapes (default: tuned here)."""
     import torch
 
     from paper_1910_01235_amd import mxe
     s = w.systems[0]
     eam = dict(w.eam, quad_rule=quad_rule)
-    plan = mxe.Plan([s], eam, w.params, precision=precision)
+    if params is None:
+        params, shapes = tuned(w, precision)
+    else:
+        shapes = {k: params.get(k) for k in ("gather_lanes", "force_lanes", "pair_block", "gather_stride")}
+    plan = mxe.Plan([s], eam, params, precision=precision)
     st, out, ws = plan.state([s]), plan.out(), plan.workspace()
     plan.run(st, out, ws, warmup, use_graph=True)
     wall, sc, prof = timed_run(plan, st, out, ws, steps, use_graph=False, profile="pair")
     ev = int(sc[mxe.S_TOTAL_EVALS])
     _, _, prof_b = timed_run(plan, st, out, ws, 1, use_graph=False, profile=True)
     n_mobile = int((s.type != 3).sum())
-    res = dict(workload=w.name, sites=s.n, precision=precision, value=s.n * ev / wall,
+    res = dict(workload=w.name, sites=s.n, precision=precision, launch_shapes=shapes,
+               value=s.n * ev / wall,
                unit="site-evals/s", site_steps_per_s=n_mobile * steps / wall,
                ms_per_step=wall / steps * 1e3, steps=steps, evals=ev,
                pairs_per_eval=float(sc[mxe.S_PAIR_EVALS]) / max(ev, 1),
@@ -415,7 +430,10 @@ def main():
     n_mobile = int((s.type != L.HOST_FIXED).sum())
     log(f"workload {w.name}: {n} sites, warmup {args.warmup}, steps {args.steps}")
 
-    plan = mxe.Plan([s], w.eam, w.params, precision="fp64")
+    t0 = time.perf_counter()
+    params, shapes = tuned(w, "fp64")
+    log(f"launch shapes {shapes} ({time.perf_counter() - t0:.1f} s)")
+    plan = mxe.Plan([s], w.eam, params, precision="fp64")
     st, out, ws = plan.state([s]), plan.out(), plan.workspace()
     plan.run(st, out, ws, args.warmup, use_graph=True)
     torch.cuda.synchronize()
@@ -488,7 +506,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "sites": n, "vacancies": int((s.x == 0).sum()),
                    "T_K": s.T, "quadrature_nodes": 27, "max_relax": w.params["max_relax"],
-                   "precision": "fp64", "launch": "eager; HIP events around the pair kernel"},
+                   "precision": "fp64", "launch": "eager; HIP events around the pair kernel",
+                   "launch_shapes": shapes},
         "site_steps_per_s": site_steps,
         "evals_in_timed_steps": evals,
         "list_builds_in_timed_steps": int(sc[mxe.S_REBUILDS]),
@@ -513,20 +532,21 @@ def main():
     del st, out, ws, plan
     torch.cuda.empty_cache()
     if "fp32" in legs:
-        result["fp32_mixed"] = fullsize_leg(w, "fp32", args.steps, args.warmup)
+        result["fp32_mixed"] = fullsize_leg(w, "fp32", args.steps, args.warmup, params=params)
         log(f"fp32 leg: {result['fp32_mixed']['value']:.4g} site-evals/s")
     if "degree3" in legs:
         # the paper's own degree-3 rule (12 nodes in the pair's 6-D space)
         result["degree3"] = {}
         for prec in ("fp64", "fp32"):
-            result["degree3"][prec] = fullsize_leg(w, prec, args.steps, args.warmup, quad_rule=1)
+            result["degree3"][prec] = fullsize_leg(w, prec, args.steps, args.warmup, quad_rule=1,
+                                                   params=params)
             log(f"degree-3 {prec} leg: {result['degree3'][prec]['value']:.4g} site-evals/s")
     if "variants" in legs:
         # state variants on the same workload: site temperatures, reservoir sites
         result["variants"] = {}
         rng = np.random.default_rng(3)
         for name in ("site_temperature", "reservoirs"):
-            pv = mxe.Plan([s], w.eam, w.params, precision="fp64")
+            pv = mxe.Plan([s], w.eam, params, precision="fp64")
             stv, outv, wsv = pv.state([s]), pv.out(), pv.workspace()
             if name == "site_temperature":
                 stv.T_site = torch.as_tensor(900.0 + 200.0 * s.q[:, 0] / s.box[0], device="cuda")

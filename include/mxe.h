@@ -123,6 +123,11 @@ typedef struct {
     /* launch shape: lanes per site in the force/mu gather (0 = 16; 8, 16, 32,
      * 64), performance only as gather_lanes */
     int force_lanes;
+    /* launch shape: the gathers visit each XCD's chunks of 256 sites S apart
+     * (0 = 1: in order). Best when S is the number of chunks between a site and
+     * its neighbours one lattice layer away (25 for 40^3 FCC cells in lattice
+     * order); performance only, results are bitwise the same for every S */
+    int gather_stride;
 } mxe_params;
 
 typedef struct {

@@ -1,11 +1,17 @@
 """Launch-shape autotuner for the evaluation kernels.
 
-Three launch shapes change speed but not the method: the lanes per site of
-the density gather and of the force gather (8, 16, 32, 64 each) and the block
-size of the pair quadrature kernel (64, 128, 256). The tuner times every
-candidate on the workload at hand (HIP events around each kernel launch,
-through the library's profiling switch), keeps the fastest of each, and caches
-the choice per size bucket, precision and lattice kind in a JSON file.
+Four launch shapes change speed but not the method: the lanes per site of
+the density gather and of the force gather (8, 16, 32, 64 each), the block
+size of the pair quadrature kernel (64, 128, 256) and the gathers' chunk
+visit stride. The tuner times every candidate on the workload at hand (HIP
+events around each kernel launch, through the library's profiling switch),
+keeps the fastest of each, and caches the choice per size bucket, precision
+and lattice kind in a JSON file.
+
+Stride candidates come from the systems' own site order: the index distance
+from a site to its nearest neighbours one lattice layer away, in chunks of
+256 sites (the gathers then read a pair block from its second end while it is
+still cached), with half and one and a half times that, and 1 (plain order).
 """
 from __future__ import annotations
 
@@ -17,6 +23,7 @@ from . import lattice as L
 from . import mxe
 
 GATHER_LANES = (8, 16, 32, 64)
+CHUNK = 256  # sites per chunk of the gathers
 PAIR_BLOCKS = (64, 128, 256)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mxe_autotune.json")
 
@@ -69,9 +76,35 @@ def _time_kernels(systems, eam, params, precision, reps, **shape):
     return ms
 
 
+def layer_stride(systems, n_probe: int = 512, seed: int = 0) -> int:
+    """Chunks between a site and its farthest first-shell neighbour in index order
+    (neighbours across a periodic wrap excluded): the 90th percentile over probe
+    sites of the largest system (in a lattice order with a basis, only some
+    basis sites reach into the next layer); 1 if it has fewer than two chunks."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    s = max(systems, key=lambda t: t.n)
+    if s.n < 2 * CHUNK:
+        return 1
+    box = np.array([b if p else 0.0 for b, p in zip(s.box, s.periodic)])
+    q = s.q - np.floor(s.q / np.where(box > 0, box, 1.0)) * box if box.any() else s.q
+    tree = cKDTree(q, boxsize=np.where(box > 0, box, np.ptp(s.q, axis=0) * 4 + 100.0))
+    rng = np.random.default_rng(seed)
+    probe = rng.choice(s.n, min(n_probe, s.n), replace=False)
+    d, nb = tree.query(q[probe], k=13)
+    off = nb - probe[:, None]
+    off = np.where((off > 0) & (off < s.n // 2) & (d < 1.25 * d[:, 1:2]), off, 0).max(axis=1)
+    return max(1, int(round(float(np.percentile(off, 90)) / CHUNK)))
+
+
+def stride_candidates(systems):
+    s0 = layer_stride(systems)
+    return sorted({1, max(1, s0 // 2), s0, s0 + s0 // 2})
+
+
 def tune(systems, eam: dict, params: dict, precision: str = "fp64", reps: int = 5) -> dict:
     """Time every candidate shape on these systems; return the fastest and the timings."""
-    timings = {"gather_lanes": {}, "force_lanes": {}, "pair_block": {}}
+    timings = {"gather_lanes": {}, "force_lanes": {}, "pair_block": {}, "gather_stride": {}}
     for g in GATHER_LANES:  # both gathers at once: each is timed on its own
         ms = _time_kernels(systems, eam, params, precision, reps, gather_lanes=g, force_lanes=g)
         timings["gather_lanes"][g] = ms["density"]
@@ -82,7 +115,13 @@ def tune(systems, eam: dict, params: dict, precision: str = "fp64", reps: int = 
     best_g = min(timings["gather_lanes"], key=timings["gather_lanes"].get)
     best_f = min(timings["force_lanes"], key=timings["force_lanes"].get)
     best_b = min(timings["pair_block"], key=timings["pair_block"].get)
+    for st in stride_candidates(systems):  # with the tuned widths; both gathers together
+        ms = _time_kernels(systems, eam, params, precision, reps, gather_lanes=best_g,
+                           force_lanes=best_f, gather_stride=st)
+        timings["gather_stride"][st] = ms["density"] + ms["force"]
+    best_s = min(timings["gather_stride"], key=timings["gather_stride"].get)
     return dict(gather_lanes=int(best_g), force_lanes=int(best_f), pair_block=int(best_b),
+                gather_stride=int(best_s),
                 timings_ms={k: {str(a): round(b, 5) for a, b in v.items()} for k, v in timings.items()})
 
 
@@ -91,11 +130,11 @@ def tuned_params(systems, eam: dict, params: dict, precision: str = "fp64", cach
     """params with the tuned launch shapes (tuned now, or taken from the cache)."""
     key = bucket(systems, precision, int(params.get("quad_rule", eam.get("quad_rule", 0))))
     hit = None if (cache is None or retune) else cache.get(key)
-    if hit is not None and "force_lanes" not in hit:
-        hit = None  # written before the force gather had a shape of its own
+    if hit is not None and ("force_lanes" not in hit or "gather_stride" not in hit):
+        hit = None  # written before these shapes existed
     if hit is None:
         hit = tune(systems, eam, params, precision, reps)
         if cache is not None:
             cache.put(key, hit)
     return dict(params, gather_lanes=hit["gather_lanes"], force_lanes=hit["force_lanes"],
-                pair_block=hit["pair_block"]), hit
+                pair_block=hit["pair_block"], gather_stride=hit["gather_stride"]), hit

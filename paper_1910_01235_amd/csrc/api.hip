@@ -44,6 +44,7 @@ struct mxe_plan {
     bool resume = false;         // calls rebuild only dirty slots
     bool tables_dirty = true;    // chunk tables changed since the last upload
     void* tables_ws = nullptr;   // workspace that holds the uploaded tables
+    void* lists_ws = nullptr;    // workspace whose neighbour lists this plan built
     std::vector<SysDesc> sys;
     std::vector<Chunk> chunks, pchunks;
     // cells in use: entry 0 holds their count, entries 1.. (system, global cell);
@@ -223,6 +224,8 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     if (p.force_lanes != 0 && p.force_lanes != 8 && p.force_lanes != 16 && p.force_lanes != 32 &&
         p.force_lanes != 64)
         return fail(MXE_EINVAL, "force_lanes must be 0, 8, 16, 32 or 64");
+    if (p.gather_stride < 0 || p.gather_stride > 4096)
+        return fail(MXE_EINVAL, "gather_stride must lie in [0, 4096]");
     if (p.pair_block != 0 && p.pair_block != 64 && p.pair_block != 128 && p.pair_block != 256)
         return fail(MXE_EINVAL, "pair_block must be 0, 64, 128 or 256");
     if (p.quad_rule != MXE_QUAD_GH27 && p.quad_rule != MXE_QUAD_DEGREE3)
@@ -278,6 +281,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     m.Qm = p.Qm;
     m.gather_lanes = p.gather_lanes ? p.gather_lanes : 8;
     m.force_lanes = p.force_lanes ? p.force_lanes : 16;
+    m.gather_stride = p.gather_stride ? p.gather_stride : 1;
     m.pair_block = p.pair_block ? p.pair_block : 256;
     m.quad_rule = p.quad_rule;
     // near-minimax remainder polynomials of node_poly.h
@@ -507,16 +511,23 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     return MXE_OK;
 }
 
+// What a call builds first: the neighbour lists (evaluate, relax), the lists
+// and the bonds (run), or the bonds alone (step).
+enum CallBuild { BUILD_LISTS, BUILD_LISTS_BONDS, BUILD_BONDS };
+
 // Tables are re-uploaded at every call so a workspace needs no separate setup.
 // Uploads the system descriptors (with this call's rebuild requests) and, when
 // they changed or the workspace differs, the chunk tables; then initialises
-// the call and builds the lists of every system that must be rebuilt.
-mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, bool bonds) {
+// the call and builds the lists of every system that must be rebuilt (and the
+// bonds), or only the bonds.
+mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, CallBuild what) {
     P->prof_last = -1;  // the untimed launches below break the profiling chain
-    // a workspace the plan has not used before holds no lists: build everything
+    const bool lists = what != BUILD_BONDS;
+    // a workspace the plan has not built lists in holds none: build everything
     const bool new_ws = P->tables_ws != (void*)d.sys;
+    const bool new_lists = P->lists_ws != (void*)d.sys;
     for (int k = 0; k < P->n_sys; ++k)
-        P->sys[k].force_build = (!P->resume || new_ws || P->dirty[k]) ? 1 : 0;
+        P->sys[k].force_build = (lists && (!P->resume || new_lists || P->dirty[k])) ? 1 : 0;
     HIP_OK(hipMemcpyAsync(d.sys, P->sys.data(), sizeof(SysDesc) * P->sys.size(), hipMemcpyHostToDevice, s));
     if (P->tables_dirty || new_ws) {
         HIP_OK(hipMemcpyAsync(d.chunks, P->chunks.data(), sizeof(Chunk) * P->chunks.size(),
@@ -528,10 +539,15 @@ mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, bool bonds) {
         P->tables_dirty = false;
         P->tables_ws = (void*)d.sys;
     }
-    std::fill(P->dirty.begin(), P->dirty.end(), 0);
     launch_ws_init(d, s);
     launch_sys_init(d, P->model, s);
-    launch_build(d, P->model, bonds, true, s);
+    if (lists) {
+        std::fill(P->dirty.begin(), P->dirty.end(), 0);
+        P->lists_ws = (void*)d.sys;
+        launch_build(d, P->model, what == BUILD_LISTS_BONDS, true, s);
+    } else {
+        launch_bonds(d, P->model, s);
+    }
     HIP_OK(hipGetLastError());
     return MXE_OK;
 }
@@ -616,7 +632,7 @@ extern "C" mxe_status mxe_evaluate(mxe_plan* P, const mxe_state* st, const mxe_o
     mxe_status r = make_dev(P, st, out, ws, ws_bytes, &d);
     if (r != MXE_OK) return r;
     hipStream_t s = (hipStream_t)stream;
-    r = begin_call(P, d, s, false);
+    r = begin_call(P, d, s, BUILD_LISTS);
     if (r != MXE_OK) return r;
     launch_relax_init(d, P->model, s);
     enqueue_eval(P, d, s);
@@ -633,7 +649,7 @@ extern "C" mxe_status mxe_relax(mxe_plan* P, const mxe_state* st, const mxe_out*
     mxe_status r = make_dev(P, st, out, ws, ws_bytes, &d);
     if (r != MXE_OK) return r;
     hipStream_t s = (hipStream_t)stream;
-    r = begin_call(P, d, s, false);
+    r = begin_call(P, d, s, BUILD_LISTS);
     if (r != MXE_OK) return r;
     enqueue_relax(P, d, s);
     HIP_OK(hipGetLastError());
@@ -648,7 +664,7 @@ extern "C" mxe_status mxe_step(mxe_plan* P, const mxe_state* st, const mxe_out* 
     mxe_status r = make_dev(P, st, out, ws, ws_bytes, &d);
     if (r != MXE_OK) return r;
     hipStream_t s = (hipStream_t)stream;
-    r = begin_call(P, d, s, true);
+    r = begin_call(P, d, s, BUILD_BONDS);
     if (r != MXE_OK) return r;
     timed(P, MXE_K_MASTER, s, [&] { launch_master(d, P->model, dt_in, s); });
     HIP_OK(hipGetLastError());
@@ -663,7 +679,7 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
     mxe_status r = make_dev(P, st, out, ws, ws_bytes, &d);
     if (r != MXE_OK) return r;
     hipStream_t s = (hipStream_t)stream;
-    r = begin_call(P, d, s, true);
+    r = begin_call(P, d, s, BUILD_LISTS_BONDS);
     if (r != MXE_OK) return r;
     if (!use_graph || P->prof_on) {
         for (int k = 0; k < n_steps; ++k) enqueue_diffusion_step(P, d, s);
@@ -752,9 +768,9 @@ extern "C" mxe_status mxe_run_noalloc(mxe_plan* P, const mxe_state* st, const mx
     hipStream_t s = (hipStream_t)stream;
     // Any call on this device may have overwritten the scratch since this plan
     // last used it: upload every table and rebuild every list and bond.
-    P->tables_ws = nullptr;
-    r = begin_call(P, d, s, true);
-    P->tables_ws = nullptr;
+    P->tables_ws = P->lists_ws = nullptr;
+    r = begin_call(P, d, s, BUILD_LISTS_BONDS);
+    P->tables_ws = P->lists_ws = nullptr;
     if (r != MXE_OK) return r;
     for (int k = 0; k < n_steps; ++k) enqueue_diffusion_step(P, d, s);
     HIP_OK(hipGetLastError());

@@ -505,7 +505,7 @@ template <typename T, int kLPS>
 __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
     constexpr int kGroups = kChunk / kLPS;
     // kGatherSplit blocks per site chunk, each taking a contiguous part of it
-    const int ub = xcd_chunk(d.n_chunks * kGatherSplit);
+    const int ub = xcd_unit_strided(d.n_chunks, kGatherSplit, m.gather_stride);
     if (ub >= d.n_chunks * kGatherSplit) return;
     const Chunk ch = d.chunks[ub / kGatherSplit];
     constexpr int kPart = kChunk / kGatherSplit;
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ double red[kGroups][6];
     // kForceSplit blocks per site chunk, each taking a contiguous part of it
     // and writing its own partial row (k_force_fold combines a chunk's rows)
-    const int ub = xcd_chunk(d.n_chunks * kForceSplit);
+    const int ub = xcd_unit_strided(d.n_chunks, kForceSplit, m.gather_stride);
     if (ub >= d.n_chunks * kForceSplit) return;
     const int cb = ub / kForceSplit;
     constexpr int kPart = kChunk / kForceSplit;
@@ -852,20 +852,20 @@ void launch_pair_t(const Dev& d, const Model& m, int bs, hipStream_t s) {
 template <typename T>
 void launch_density_t(const Dev& d, const Model& m, int lps, hipStream_t s) {
     switch (lps) {
-        case 8: k_density<T, 8><<<xcd_grid(d.n_chunks * kGatherSplit), kChunk, 0, s>>>(d, m); break;
-        case 32: k_density<T, 32><<<xcd_grid(d.n_chunks * kGatherSplit), kChunk, 0, s>>>(d, m); break;
-        case 64: k_density<T, 64><<<xcd_grid(d.n_chunks * kGatherSplit), kChunk, 0, s>>>(d, m); break;
-        default: k_density<T, 16><<<xcd_grid(d.n_chunks * kGatherSplit), kChunk, 0, s>>>(d, m); break;
+        case 8: k_density<T, 8><<<xcd_grid_chunks(d.n_chunks, kGatherSplit), kChunk, 0, s>>>(d, m); break;
+        case 32: k_density<T, 32><<<xcd_grid_chunks(d.n_chunks, kGatherSplit), kChunk, 0, s>>>(d, m); break;
+        case 64: k_density<T, 64><<<xcd_grid_chunks(d.n_chunks, kGatherSplit), kChunk, 0, s>>>(d, m); break;
+        default: k_density<T, 16><<<xcd_grid_chunks(d.n_chunks, kGatherSplit), kChunk, 0, s>>>(d, m); break;
     }
 }
 
 template <typename T>
 void launch_force_t(const Dev& d, const Model& m, int lps, hipStream_t s) {
     switch (lps) {
-        case 8: k_force<T, 8><<<xcd_grid(d.n_chunks * kForceSplit), kChunk, 0, s>>>(d, m); break;
-        case 32: k_force<T, 32><<<xcd_grid(d.n_chunks * kForceSplit), kChunk, 0, s>>>(d, m); break;
-        case 64: k_force<T, 64><<<xcd_grid(d.n_chunks * kForceSplit), kChunk, 0, s>>>(d, m); break;
-        default: k_force<T, 16><<<xcd_grid(d.n_chunks * kForceSplit), kChunk, 0, s>>>(d, m); break;
+        case 8: k_force<T, 8><<<xcd_grid_chunks(d.n_chunks, kForceSplit), kChunk, 0, s>>>(d, m); break;
+        case 32: k_force<T, 32><<<xcd_grid_chunks(d.n_chunks, kForceSplit), kChunk, 0, s>>>(d, m); break;
+        case 64: k_force<T, 64><<<xcd_grid_chunks(d.n_chunks, kForceSplit), kChunk, 0, s>>>(d, m); break;
+        default: k_force<T, 16><<<xcd_grid_chunks(d.n_chunks, kForceSplit), kChunk, 0, s>>>(d, m); break;
     }
 }
 

@@ -184,11 +184,24 @@ __global__ __launch_bounds__(kChunk) void k_bin(Dev d, Model m) {
     d.slot_of[i] = atomicAdd(&d.cell_count[cell], 1);
 }
 
+// Bins every site for a bonds-only build: the cells as k_bin forms them, but
+// no rebuild decision and no change to the lists' reference positions.
+__global__ __launch_bounds__(kChunk) void k_bond_bin(Dev d) {
+    const Chunk ch = d.chunks[blockIdx.x];
+    const int i = ch.start + threadIdx.x;
+    if (i >= ch.end) return;
+    const SysDesc& S = d.sys[ch.sys];
+    const int64_t cell = site_cell(S, d.qx[i], d.qy[i], d.qz[i]);
+    d.cell_of[i] = (int)cell;
+    d.slot_of[i] = atomicAdd(&d.cell_count[cell], 1);
+}
+
 // One block per system: cell offsets into the per-system range of cell_sites.
-__global__ __launch_bounds__(1024) void k_cell_scan(Dev d) {
+// all: every system (the bonds-only build), else the systems being rebuilt.
+__global__ __launch_bounds__(1024) void k_cell_scan(Dev d, int all) {
     __shared__ int lds[1024];
     const int s = blockIdx.x;
-    if (!d.ctl[s].rebuild) return;
+    if (!all && !d.ctl[s].rebuild) return;
     const SysDesc& S = d.sys[s];
     const int64_t nc = S.n_cells;
     const int per = (int)((nc + 1023) / 1024);
@@ -205,9 +218,9 @@ __global__ __launch_bounds__(1024) void k_cell_scan(Dev d) {
 
 // Places each site in its cell and copies its position, width and type into
 // the cell-ordered records, so candidates of one cell are contiguous in memory.
-__global__ __launch_bounds__(kChunk) void k_fill(Dev d) {
+__global__ __launch_bounds__(kChunk) void k_fill(Dev d, int all) {
     const Chunk ch = d.chunks[blockIdx.x];
-    if (!d.ctl[ch.sys].rebuild) return;
+    if (!all && !d.ctl[ch.sys].rebuild) return;
     const int i = ch.start + threadIdx.x;
     if (i >= ch.end) return;
     const int pos = d.cell_start[d.cell_of[i]] + d.slot_of[i];
@@ -287,7 +300,7 @@ constexpr int kNbrGrid = 16384;  // blocks of the neighbour search at most
 // all lie beyond r_c contributes exact zeros). Rows are sorted, so they do not
 // depend on the order of the sites within a cell.
 template <int E>
-__global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
+__global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds, int bonds_only) {
     constexpr int K2 = kWave * E;
     constexpr int kWaves = kChunk / kWave;
     __shared__ int rows[kWaves][K2];
@@ -301,7 +314,7 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
     // contiguous ranges; the blocks of an XCD stride through their range.
     // With no system rebuilding, every block leaves after one load.
     const int2 a0 = d.acell[0];
-    if (a0.y == 0) return;
+    if (a0.y == 0 && !bonds_only) return;
     const int na = a0.x;
     const int per = (na + kXcd - 1) / kXcd;
     const int x0 = (int)(blockIdx.x % kXcd) * per, x1 = min(na, x0 + per);
@@ -309,11 +322,12 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
     for (int b = x0 + (int)(blockIdx.x / kXcd); b < x1; b += nq) {
         const int2 ac = d.acell[1 + b];
         const int s = ac.x, g = ac.y;
-        if (!d.ctl[s].rebuild) continue;
+        if (!bonds_only && !d.ctl[s].rebuild) continue;
         const int nsite = d.cell_count[g];
         if (nsite == 0) continue;  // both skips are uniform over the block
         const SysDesc& S = d.sys[s];
-        const bool sys_bonds = bonds != 0 && S.force_build != 0;  // bonds of other systems are kept
+        // bonds of other systems are kept, except in a bonds-only build (all systems)
+        const bool sys_bonds = bonds_only != 0 || (bonds != 0 && S.force_build != 0);
         __syncthreads();  // the previous cell's tile and stencil are no longer read
         if (wave == 0) {
             const int lc = g - (int)S.cell_off;
@@ -446,7 +460,7 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
                     const double rl =
                         reach + (d3 ? 2.449489742783178 * (double)fmaxf(sig_i, (float)rj.w)
                                     : 3.0 * (double)__builtin_sqrtf((float)(si2 + rj.w * rj.w)));
-                    const bool ok = in & (j != i) & (pair_cls(ti, jt & 3) >= 0) &
+                    const bool ok = !bonds_only & in & (j != i) & (pair_cls(ti, jt & 3) >= 0) &
                                     (dx * dx + dy * dy + dz * dz < rl * rl);
                     const unsigned long long mask = __ballot(ok);
                     const int pos = n + __popcll(mask & __lanemask_lt());
@@ -467,41 +481,43 @@ __global__ __launch_bounds__(kChunk) void k_nbr(Dev d, Model m, int bonds) {
             if (has) {
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                if (n > K) over = true;
-                const int nk = min(n, K);
-                int lo = 0;
-                int* out = d.nbr + (int64_t)i * K;
-                if (E > 1 && n <= kWave) {  // a short row: one entry per lane suffices
-                    int v[1] = {lane < n ? row[lane] : 0x7fffffff};
-                    wave_sort<1>(v, lane);
-                    if (lane < nk) {
-                        out[lane] = v[0];
-                        lo += (v[0] < i);
-                    }
-                } else {
-                    int v[E];
-#pragma unroll
-                    for (int r = 0; r < E; ++r) {
-                        const int t = r * kWave + lane;
-                        v[r] = t < min(n, K2) ? row[t] : 0x7fffffff;
-                    }
-                    wave_sort<E>(v, lane);
-#pragma unroll
-                    for (int r = 0; r < E; ++r) {
-                        const int t = r * kWave + lane;
-                        if (t < nk) {
-                            out[t] = v[r];
-                            lo += (v[r] < i);
+                if (!bonds_only) {  // the row (not in a bonds-only build)
+                    if (n > K) over = true;
+                    const int nk = min(n, K);
+                    int lo = 0;
+                    int* out = d.nbr + (int64_t)i * K;
+                    if (E > 1 && n <= kWave) {  // a short row: one entry per lane suffices
+                        int v[1] = {lane < n ? row[lane] : 0x7fffffff};
+                        wave_sort<1>(v, lane);
+                        if (lane < nk) {
+                            out[lane] = v[0];
+                            lo += (v[0] < i);
+                        }
+                    } else {
+                        int v[E];
+    #pragma unroll
+                        for (int r = 0; r < E; ++r) {
+                            const int t = r * kWave + lane;
+                            v[r] = t < min(n, K2) ? row[t] : 0x7fffffff;
+                        }
+                        wave_sort<E>(v, lane);
+    #pragma unroll
+                        for (int r = 0; r < E; ++r) {
+                            const int t = r * kWave + lane;
+                            if (t < nk) {
+                                out[t] = v[r];
+                                lo += (v[r] < i);
+                            }
                         }
                     }
-                }
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) lo += __shfl_xor(lo, o);
-                if (lane == 0) {
-                    d.nbr_cnt[i] = nk;
-                    d.nbr_lo[i] = lo;
-                    // owned pairs per site chunk (an integer sum: order-independent)
-                    atomicAdd(&d.chunk_up[S.chunk_first + (i - (int)S.site_off) / kChunk], nk - lo);
+    #pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) lo += __shfl_xor(lo, o);
+                    if (lane == 0) {
+                        d.nbr_cnt[i] = nk;
+                        d.nbr_lo[i] = lo;
+                        // owned pairs per site chunk (an integer sum: order-independent)
+                        atomicAdd(&d.chunk_up[S.chunk_first + (i - (int)S.site_off) / kChunk], nk - lo);
+                    }
                 }
                 if (sys_bonds) {  // uniform over the wave
                     const int B = d.bond_max, nbk = min(nb, B);
@@ -738,17 +754,30 @@ int row_pow2(int K) {
     return k2;
 }
 
+void launch_nbr(const Dev& d, const Model& m, int bonds, int bonds_only, hipStream_t s) {
+    const int gc = std::min(xcd_grid((int)d.n_cells), kNbrGrid);
+    switch (row_pow2(d.K)) {
+        case 64: k_nbr<1><<<gc, kChunk, 0, s>>>(d, m, bonds, bonds_only); break;
+        case 128: k_nbr<2><<<gc, kChunk, 0, s>>>(d, m, bonds, bonds_only); break;
+        default: k_nbr<4><<<gc, kChunk, 0, s>>>(d, m, bonds, bonds_only); break;
+    }
+}
+
+// The bonds of every system from the current positions, lists untouched: the
+// cells are binned and filled afresh (the cell counts start at zero, as at
+// every call) and the neighbour search only collects the bonds.
+void launch_bonds(const Dev& d, const Model& m, hipStream_t s) {
+    k_bond_bin<<<d.n_chunks, kChunk, 0, s>>>(d);
+    k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d, 1);
+    k_fill<<<d.n_chunks, kChunk, 0, s>>>(d, 1);
+    launch_nbr(d, m, 1, 1, s);
+}
+
 void launch_build(const Dev& d, const Model& m, bool bonds, bool finish, hipStream_t s) {
     k_bin<<<d.n_chunks, kChunk, 0, s>>>(d, m);
-    k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d);
-    k_fill<<<d.n_chunks, kChunk, 0, s>>>(d);
-    const int gc = std::min(xcd_grid((int)d.n_cells), kNbrGrid);
-    const int nb = bonds ? 1 : 0;
-    switch (row_pow2(d.K)) {
-        case 64: k_nbr<1><<<gc, kChunk, 0, s>>>(d, m, nb); break;
-        case 128: k_nbr<2><<<gc, kChunk, 0, s>>>(d, m, nb); break;
-        default: k_nbr<4><<<gc, kChunk, 0, s>>>(d, m, nb); break;
-    }
+    k_cell_scan<<<d.n_sys, 1024, 0, s>>>(d, 0);
+    k_fill<<<d.n_chunks, kChunk, 0, s>>>(d, 0);
+    launch_nbr(d, m, bonds ? 1 : 0, 0, s);
     k_half<<<d.n_chunks, kChunk, 0, s>>>(d);
     k_pid<<<xcd_grid(d.n_chunks), kPidThreads, 0, s>>>(d);
     k_pair_order<<<d.n_pchunks, kOrderThreads, 0, s>>>(d);

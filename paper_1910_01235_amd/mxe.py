@@ -52,7 +52,8 @@ class Params(C.Structure):
                 ("fire_nmin", C.c_int), ("sigma_min", C.c_double), ("sigma_cap", C.c_double),
                 ("skin", C.c_double), ("r_bond", C.c_double), ("k_max", C.c_int),
                 ("bond_max", C.c_int), ("precision", C.c_int), ("gather_lanes", C.c_int),
-                ("pair_block", C.c_int), ("quad_rule", C.c_int), ("force_lanes", C.c_int)]
+                ("pair_block", C.c_int), ("quad_rule", C.c_int), ("force_lanes", C.c_int),
+                ("gather_stride", C.c_int)]
 
 
 class System(C.Structure):
@@ -148,7 +149,8 @@ _PARAM_MAP = dict(nu0="nu0", Qm="Qm", kin_c="kin_c", dt_safety="dt_safety",
                   alpha0="fire_alpha0", finc="fire_finc", fdec="fire_fdec", falpha="fire_falpha",
                   nmin="fire_nmin", sigma_min="sigma_min", r_bond="r_bond", sigma_cap="sigma_cap",
                   skin="skin", k_max="k_max", bond_max="bond_max", gather_lanes="gather_lanes",
-                  pair_block="pair_block", quad_rule="quad_rule", force_lanes="force_lanes")
+                  pair_block="pair_block", quad_rule="quad_rule", force_lanes="force_lanes",
+                  gather_stride="gather_stride")
 
 
 def make_params(params: dict, precision: str = "fp64", **over) -> Params:

@@ -37,6 +37,20 @@ def test_plan_validates_launch_shapes():
         mxe.Plan(w.systems, w.eam, w.params, force_lanes=24)
     with pytest.raises(mxe.MxeError, match="pair_block"):
         mxe.Plan(w.systems, w.eam, w.params, pair_block=512)
+    for st in (0, 1, 25, 4096):
+        mxe.Plan(w.systems, w.eam, w.params, gather_stride=st)
+    with pytest.raises(mxe.MxeError, match="gather_stride"):
+        mxe.Plan(w.systems, w.eam, w.params, gather_stride=-1)
+
+
+def test_layer_stride_from_site_order():
+    """FCC cells in lattice order: one layer of 40 x 40 cells is 6,400 sites, of
+    32 x 32 cells 4,096 (25 and 16 chunks of 256; the farthest first-shell
+    neighbour sits a few sites further)."""
+    assert autotune.layer_stride(L.config1(1).systems) == 26
+    assert autotune.layer_stride(L.config2(2).systems) == 16
+    assert autotune.layer_stride([L.vacancy_bulk(4, 0, 800.0, 0)]) == 1  # one chunk
+    assert autotune.stride_candidates(L.config1(1).systems) == [1, 13, 26, 39]
 
 
 def test_profile_modes_are_validated():

@@ -159,6 +159,49 @@ def test_master_step_matches_oracle(mx):
     assert plan.scalars(out)[0, mx.S_DT] == 1e-9
 
 
+def test_step_builds_bonds_only_and_keeps_lists(mx):
+    """mxe_step builds the kinetic bonds alone: in resume mode the neighbour rows of
+    the previous evaluation are left as they were and the next evaluation reuses
+    them; on a workspace where no lists were built, the next evaluation builds them."""
+    s = L.jitter(L.alloy_bulk(5, 0.3, 900.0, 7), 18, xr=(0.05, 0.95))
+    plan = mx.Plan([s], EAM, P)
+    plan.set_resume(True)
+    st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+    plan.evaluate(st, out, ws)
+    torch.cuda.synchronize()
+    before = plan.lists(ws)
+    plan.step(st, out, ws)
+    torch.cuda.synchronize()
+    after = plan.lists(ws)
+    assert np.array_equal(before["nbr_count"], after["nbr_count"])
+    assert np.array_equal(before["nbr"], after["nbr"])
+    nb, bl = O.bonds(s.box, s.periodic, s.q, s.type, P["r_bond"])
+    assert np.array_equal(after["bond_count"], nb)
+    valid = np.arange(bl.shape[1])[None, :] < nb[:, None]
+    assert np.array_equal(np.where(valid, after["bond"][:, :bl.shape[1]], -1), np.where(valid, bl, -1))
+    x1 = st.x.cpu().numpy()
+    assert np.abs(x1 - s.x).max() > 0
+    plan.evaluate(st, out, ws)  # resume: the lists of the first evaluation
+    torch.cuda.synchronize()
+    o = O.evaluate(EAM, s.box, s.periodic, s.T, s.q, s.sigma, x1, s.type)
+    g = gpu_arrays(plan, st, out)
+    assert rel_err(g["force"], o["force"], 1e-2) < 1e-10
+    assert rel_err(g["mu"], o["mu"], 1e-2) < 1e-10
+    # a fresh workspace: a step first (no lists), then an evaluation in resume mode
+    plan2 = mx.Plan([s], EAM, P)
+    plan2.set_resume(True)
+    st2, out2, ws2 = plan2.state([s]), plan2.out(), plan2.workspace()
+    plan2.step(st2, out2, ws2)  # mu = 0: the linear law D sum_j (x_j - x_i)
+    plan2.evaluate(st2, out2, ws2)
+    torch.cuda.synchronize()
+    x2 = st2.x.cpu().numpy()
+    o2 = O.evaluate(EAM, s.box, s.periodic, s.T, s.q, s.sigma, x2, s.type)
+    g2 = gpu_arrays(plan2, st2, out2)
+    assert int(plan2.scalars(out2)[0, mx.S_STATUS]) & mx.FATAL_STATUS == 0
+    assert rel_err(g2["force"], o2["force"], 1e-2) < 1e-10
+    assert rel_err(g2["rho_bar"], o2["rho_bar"], 1.0) < 1e-10
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_run_c0_matches_oracle(mx, use_graph):
     w = L.config0(0)
