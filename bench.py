@@ -49,16 +49,17 @@ BYTES_DENSITY_PER_SITE = 4 + 1 + 8 + 8 + 8 * 5 + 64
 BREAKDOWN_STEPS = 2
 
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
-# this bench (--steps 2 --warmup 1 --no-extras --no-cpu-baseline --calib-copy),
+# this bench (--steps 2 --warmup 1 --no-extras --no-cpu-baseline --calib-copy
+# --shapes gather_lanes=8,force_lanes=16,pair_block=256,gather_stride=26),
 # KiB per dispatch averaged over the run's dispatches, scaled by what the same
 # counters read for a 1 GiB device copy (FETCH x 2, WRITE x 1). Valid only for
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="75dd4a5669ce5013",
-    pair=dict(fetch_kib=159583.6, write_kib=1019787.0),
-    force=dict(fetch_kib=900776.3, write_kib=13650.1),
-    density=dict(fetch_kib=172829.2, write_kib=26951.2),
+    sources_sha256_16="9e6c48511664837a",
+    pair=dict(fetch_kib=160083.9, write_kib=1019787.0),
+    force=dict(fetch_kib=896910.9, write_kib=13688.5),
+    density=dict(fetch_kib=137353.4, write_kib=27090.6),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -72,11 +73,17 @@ def counter_traffic(family: str):
 
 
 # VALU counters of the pair kernel per dispatch (summed over every shader
-# engine), from a rocprofv3 --pmc run of this bench (--steps 2 --warmup 1
-# --no-extras --no-cpu-baseline). SQ_INSTS_* count wave instructions;
+# engine), from two rocprofv3 --pmc runs of this bench (the HBM counters'
+# options without --calib-copy). SQ_INSTS_* count wave instructions;
 # VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
 # Valid only for the sources they were taken on.
-VALU_COUNTERS = dict(sources_sha256_16="", pair={})
+VALU_COUNTERS = dict(
+    sources_sha256_16="9e6c48511664837a",
+    pair=dict(SQ_INSTS_VALU=223472590.2, SQ_INSTS_VALU_FMA_F64=121838857.9,
+              SQ_INSTS_VALU_MUL_F64=29486458.4, SQ_INSTS_VALU_ADD_F64=12554676.0,
+              SQ_INSTS_VALU_TRANS_F64=3222591.1, SQ_INSTS_VALU_FLOPS_FP64=288942441.8,
+              VALUBusy=74.81, VALUUtilization=90.39),
+)
 
 
 def _sources_hash() -> str:
@@ -97,7 +104,9 @@ def valu_counters(pair_avg_s: float):
     lane_ops = c["SQ_INSTS_VALU"] * 64.0
     f64 = (c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_MUL_F64"] + c["SQ_INSTS_VALU_ADD_F64"] +
            c["SQ_INSTS_VALU_TRANS_F64"]) * 64.0
+    flops = c["SQ_INSTS_VALU_FLOPS_FP64"] * 64.0
     return dict(VALUBusy_pct=c["VALUBusy"], VALUUtilization_pct=c.get("VALUUtilization"),
+                fp64_tflops=flops / pair_avg_s / 1e12, fp64_flops_frac=flops / pair_avg_s / 78.6e12,
                 valu_lane_ops_per_s=lane_ops / pair_avg_s,
                 valu_issue_frac=lane_ops / pair_avg_s / (PEAK_FP64_TOPS * 1e12),
                 fp64_lane_ops_per_s=f64 / pair_avg_s,
@@ -213,7 +222,7 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
     base = dict(L.DEFAULT_PARAMS)
     # launch shapes from the project's autotuner, on this batch
     params, tuned = autotune.tuned_params(systems, L.DEFAULT_EAM, base, cache=None, reps=2)
-    shapes = {k: tuned[k] for k in ("gather_lanes", "force_lanes", "pair_block")}
+    shapes = {k: tuned[k] for k in ("gather_lanes", "force_lanes", "pair_block", "gather_stride")}
     log(f"serving: {len(systems)} requests, {n_tot} sites, tuned shapes {shapes}")
 
     # all requests in one batched plan: the capacity
@@ -408,6 +417,8 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=50)
     ap.add_argument("--serve-rates", default="0.25,0.5,0.8,1.0,2.0",
                     help="arrival rates as multiples of the batched capacity")
+    ap.add_argument("--shapes", default="",
+                    help="launch shapes of the 256k-site legs as k=v,... (default: the autotuner's)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -431,7 +442,11 @@ def main():
     log(f"workload {w.name}: {n} sites, warmup {args.warmup}, steps {args.steps}")
 
     t0 = time.perf_counter()
-    params, shapes = tuned(w, "fp64")
+    if args.shapes:
+        shapes = {k: int(v) for k, v in (kv.split("=") for kv in args.shapes.split(","))}
+        params = dict(w.params, **shapes)
+    else:
+        params, shapes = tuned(w, "fp64")
     log(f"launch shapes {shapes} ({time.perf_counter() - t0:.1f} s)")
     plan = mxe.Plan([s], w.eam, params, precision="fp64")
     st, out, ws = plan.state([s]), plan.out(), plan.workspace()
