@@ -197,8 +197,12 @@ def sampled_errors(workload, plan, st, out, ws, precision, n_sample=64, seed=0):
                 bar=1e-10 if precision == "fp64" else 1e-5)
 
 
+RELAX_CHUNK_BATCHED = 4   # relaxation chunk of the batched plan and the server pool
+RELAX_CHUNK_SINGLE = 2    # and of the one-at-a-time path (small systems, short chunks)
+
+
 def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
-                  budget_gb: float = 24.0):
+                  budget_gb: float = 24.0, before_rates=(0.25, 1.0)):
     """The serving workload: independent systems run as one batched plan, one at
     a time, and served with continuous batching at Poisson arrival rates given as
     multiples of the batched capacity.
@@ -208,7 +212,13 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
     updates. Latency = completion - arrival. The one-at-a-time path is measured
     once (every request alone, back to back); its latencies under each arrival
     stream follow from the measured service times of a first-come-first-served
-    single server."""
+    single server.
+
+    Two schedules: relaxations that end once every system of the plan has
+    converged (relax_chunk > 0; the one-at-a-time path with launch shapes tuned
+    per size octave), and the fixed sequence of max_relax + 1 iterations per
+    relaxation with the batch's shapes everywhere (`fixed_sequence`, at the
+    same absolute arrival rates for before_rates)."""
     import numpy as np
     import torch
 
@@ -220,40 +230,49 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
     systems = L.config4_requests(seed=seed, n_requests=n_requests)
     n_tot = sum(s.n for s in systems)
     base = dict(L.DEFAULT_PARAMS)
-    # launch shapes from the project's autotuner, on this batch
+    # launch shapes from the project's autotuner, on this batch, and per size octave
     params, tuned = autotune.tuned_params(systems, L.DEFAULT_EAM, base, cache=None, reps=2)
-    shapes = {k: tuned[k] for k in ("gather_lanes", "force_lanes", "pair_block", "gather_stride")}
+    shapes = {k: tuned[k] for k in autotune.SHAPES}
     log(f"serving: {len(systems)} requests, {n_tot} sites, tuned shapes {shapes}")
+    cache = autotune.Cache(path="")
+    single = {}
+    for s in systems:
+        p1, _ = autotune.tuned_params([s], L.DEFAULT_EAM, dict(base, relax_chunk=RELAX_CHUNK_SINGLE),
+                                      cache=cache, reps=3)
+        single[id(s)] = p1
+    octaves = {k: {kk: v[kk] for kk in autotune.SHAPES} for k, v in sorted(cache.data.items())}
+    log(f"serving: shapes per size octave {octaves}")
 
-    # all requests in one batched plan: the capacity
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan = mxe.Plan(systems, L.DEFAULT_EAM, params)
-    st, out, ws = plan.state(systems), plan.out(), plan.workspace()
-    plan.run(st, out, ws, n_steps, use_graph=True)
-    torch.cuda.synchronize()
-    wall_b = time.perf_counter() - t0
-    sc = plan.scalars(out)
-    evals_b = sc[:, mxe.S_TOTAL_EVALS]
-    site_evals = float(sum(s.n * e for s, e in zip(systems, evals_b)))
-    status_b = int(np.bitwise_or.reduce(sc[:, mxe.S_STATUS].astype(np.int64)))
-    del plan, st, out, ws
-    torch.cuda.empty_cache()
-    cap = len(systems) / wall_b
-    batched = dict(systems_per_s=cap, site_evals_per_s=site_evals / wall_b,
-                   site_steps_per_s=n_tot * n_steps / wall_b, wall_s=wall_b,
-                   evals_per_system_step=float(evals_b.mean() / n_steps), status=status_b)
-    log(f"serving: batched {wall_b:.1f} s, {cap:.1f} systems/s")
+    def batched(p):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = mxe.Plan(systems, L.DEFAULT_EAM, p)
+        st, out, ws = plan.state(systems), plan.out(), plan.workspace()
+        plan.run(st, out, ws, n_steps, use_graph=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sc = plan.scalars(out)
+        ev = sc[:, mxe.S_TOTAL_EVALS]
+        status = int(np.bitwise_or.reduce(sc[:, mxe.S_STATUS].astype(np.int64)))
+        x = [st.x[plan.offsets[k]:plan.offsets[k + 1]].cpu().numpy() for k in range(len(systems))]
+        del plan, st, out, ws
+        torch.cuda.empty_cache()
+        return dict(systems_per_s=len(systems) / wall,
+                    site_evals_per_s=float(sum(s.n * e for s, e in zip(systems, ev))) / wall,
+                    site_steps_per_s=n_tot * n_steps / wall, wall_s=wall,
+                    evals_per_system_step=float(ev.mean() / n_steps), status=status), x
 
-    # one at a time: a plan per request, back to back (the plain path)
-    reqs0 = serve.poisson_requests(systems, n_steps=n_steps, rate=0.0)
-    res1, one = serve.serve_one_at_a_time(
-        L.DEFAULT_EAM, params, reqs0, realtime=False,
-        progress=lambda k: log(f"serving: one at a time, {k} done") if k % 64 == 0 else None)
-    service = {r.rid: r.completed - r.admitted for r in res1}
-    log(f"serving: one at a time {one['makespan_s']:.1f} s")
+    def one_at_a_time(p, params_for, tag):
+        reqs0 = serve.poisson_requests(systems, n_steps=n_steps, rate=0.0)
+        res, st1 = serve.serve_one_at_a_time(
+            L.DEFAULT_EAM, p, reqs0, realtime=False, params_for=params_for,
+            progress=lambda k: log(f"serving: one at a time ({tag}), {k} done") if k % 128 == 0 else None)
+        log(f"serving: one at a time ({tag}) {st1['makespan_s']:.1f} s")
+        service = {r.rid: r.completed - r.admitted for r in res}
+        return dict(systems_per_s=st1["systems_per_s"], makespan_s=st1["makespan_s"],
+                    p50_s=st1["p50_s"], p99_s=st1["p99_s"], arrivals="all at t = 0"), service, res
 
-    def fcfs(reqs):
+    def fcfs(reqs, service):
         """Latencies of a first-come-first-served single server with these service times."""
         c, lat = 0.0, []
         for r in sorted(reqs, key=lambda r: (r.arrival, r.rid)):
@@ -263,37 +282,57 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
         return dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                     systems_per_s=len(lat) / c)
 
-    # served: continuous batching over a slot pool sized to the HBM budget
-    per_site = serve.bytes_per_site(L.DEFAULT_EAM, params)
-    caps = serve.pool_capacities(budget_gb * 1e9, per_site)
-    srv = serve.Server(L.DEFAULT_EAM, params, caps)
-    warm = serve.poisson_requests([L.vacancy_bulk(5, 1, 800.0, 0)], n_steps=1, rate=0.0)
-    srv.serve(warm, realtime=False)  # records the step graph
-    served = []
-    for f in rate_factors:
-        rate = f * cap
-        reqs = serve.poisson_requests(systems, n_steps=n_steps, rate=rate, seed=seed)
-        res, rejected, st_s = srv.serve(
-            reqs, realtime=True,
-            progress=lambda k: log(f"serving: rate {f}, {k} done") if k % 64 == 0 else None)
-        served.append(dict(
-            rate_factor=f, arrival_rate_per_s=rate, systems_per_s=st_s["systems_per_s"],
-            site_steps_per_s=st_s["site_steps_per_s"], p50_s=st_s["p50_s"], p99_s=st_s["p99_s"],
-            makespan_s=st_s["makespan_s"], gpu_steps=st_s["gpu_steps"], rejected=len(rejected),
-            status=int(np.bitwise_or.reduce([r.status for r in res])) if res else 0,
-            one_at_a_time=fcfs(reqs)))
-        log(f"serving: rate {f} x capacity: {st_s['systems_per_s']:.1f} systems/s, "
-            f"p50 {st_s['p50_s']:.2f} s, p99 {st_s['p99_s']:.2f} s")
-    out = dict(requests=len(systems), sites=n_tot, steps_per_request=n_steps,
-               max_relax=params["max_relax"], shapes=shapes, batched=batched,
-               one_at_a_time=dict(systems_per_s=one["systems_per_s"], makespan_s=one["makespan_s"],
-                                  p50_s=one["p50_s"], p99_s=one["p99_s"],
-                                  arrivals="all at t = 0"),
-               batched_vs_one_at_a_time=cap / one["systems_per_s"],
-               served=served, slots=len(caps), footprint_gb=srv.footprint_bytes / 1e9)
-    del srv
-    torch.cuda.empty_cache()
-    return out
+    def served(p, rates, service, tag):
+        per_site = serve.bytes_per_site(L.DEFAULT_EAM, p)
+        caps = serve.pool_capacities(budget_gb * 1e9, per_site)
+        srv = serve.Server(L.DEFAULT_EAM, p, caps)
+        warm = serve.poisson_requests([L.vacancy_bulk(5, 1, 800.0, 0)], n_steps=1, rate=0.0)
+        srv.serve(warm, realtime=False)  # records the step graphs
+        rows = []
+        for f, rate in rates:
+            reqs = serve.poisson_requests(systems, n_steps=n_steps, rate=rate, seed=seed)
+            res, rejected, st_s = srv.serve(
+                reqs, realtime=True,
+                progress=lambda k: log(f"serving ({tag}): rate {f}, {k} done") if k % 128 == 0 else None)
+            rows.append(dict(
+                rate_factor=f, arrival_rate_per_s=rate, systems_per_s=st_s["systems_per_s"],
+                site_steps_per_s=st_s["site_steps_per_s"], p50_s=st_s["p50_s"], p99_s=st_s["p99_s"],
+                makespan_s=st_s["makespan_s"], gpu_steps=st_s["gpu_steps"], rejected=len(rejected),
+                status=int(np.bitwise_or.reduce([r.status for r in res])) if res else 0,
+                one_at_a_time=fcfs(reqs, service)))
+            log(f"serving ({tag}): rate {f} x capacity: {st_s['systems_per_s']:.1f} systems/s, "
+                f"p50 {st_s['p50_s']:.2f} s, p99 {st_s['p99_s']:.2f} s")
+        fp = srv.footprint_bytes / 1e9
+        del srv
+        torch.cuda.empty_cache()
+        return rows, len(caps), fp
+
+    # early exit (the product's schedule)
+    p_b = dict(params, relax_chunk=RELAX_CHUNK_BATCHED)
+    bat, x_b = batched(p_b)
+    cap = bat["systems_per_s"]
+    log(f"serving: batched {bat['wall_s']:.1f} s, {cap:.1f} systems/s")
+    one, service, res1 = one_at_a_time(params, lambda s: single[id(s)], "early exit")
+    srv_rows, n_slots, fp = served(p_b, [(f, f * cap) for f in rate_factors], service, "early exit")
+    # fixed sequence, same absolute arrival rates
+    bat0, x_b0 = batched(params)
+    log(f"serving: batched, fixed sequence {bat0['wall_s']:.1f} s")
+    one0, service0, res0 = one_at_a_time(params, None, "fixed sequence")
+    srv0, _, _ = served(params, [(f, f * cap) for f in before_rates], service0, "fixed sequence")
+    # the batched runs differ only in the schedule: bitwise equal; the one-at-a-time
+    # runs also differ in launch shapes (lanes per site reorder sums): to rounding
+    same = all(np.array_equal(a, b) for a, b in zip(x_b, x_b0))
+    dx = max(float(np.abs(a.x - b.x).max()) for a, b in zip(sorted(res1, key=lambda r: r.rid),
+                                                            sorted(res0, key=lambda r: r.rid)))
+    return dict(requests=len(systems), sites=n_tot, steps_per_request=n_steps,
+                max_relax=params["max_relax"], shapes=shapes, shapes_one_at_a_time=octaves,
+                relax_chunk=dict(batched=RELAX_CHUNK_BATCHED, served=RELAX_CHUNK_BATCHED,
+                                 one_at_a_time=RELAX_CHUNK_SINGLE),
+                batched=bat, one_at_a_time=one, batched_vs_one_at_a_time=cap / one["systems_per_s"],
+                served=srv_rows, slots=n_slots, footprint_gb=fp,
+                fixed_sequence=dict(batched=bat0, one_at_a_time=one0, served=srv0,
+                                    batched_x_bitwise_equal=bool(same),
+                                    one_at_a_time_max_abs_dx=dx))
 
 
 def timed_run(plan, st, out, ws, steps, use_graph, profile):
@@ -320,7 +359,7 @@ def tuned(w, precision, params=None):
     from paper_1910_01235_amd import autotune
     p, hit = autotune.tuned_params(w.systems, w.eam, params or w.params, precision=precision,
                                    cache=autotune.Cache(), reps=3)
-    return p, {k: hit[k] for k in ("gather_lanes", "force_lanes", "pair_block", "gather_stride")}
+    return p, {k: hit[k] for k in autotune.SHAPES}
 
 
 def fullsize_leg(w, precision, steps, warmup, quad_rule=0, params=None):
@@ -337,7 +376,8 @@ def fullsize_leg(w, precision, steps, warmup, quad_rule=0, params=None):
     if params is None:
         params, shapes = tuned(w, precision)
     else:
-        shapes = {k: params.get(k) for k in ("gather_lanes", "force_lanes", "pair_block", "gather_stride")}
+        from paper_1910_01235_amd import autotune
+        shapes = {k: params.get(k) for k in autotune.SHAPES}
     plan = mxe.Plan([s], eam, params, precision=precision)
     st, out, ws = plan.state([s]), plan.out(), plan.workspace()
     plan.run(st, out, ws, warmup, use_graph=True)
@@ -361,7 +401,10 @@ def fullsize_leg(w, precision, steps, warmup, quad_rule=0, params=None):
 
 def c0_leg():
     """The plain-method workload end to end: 256 sites, 20 diffusion steps of up
-    to 50 FIRE updates, one graph replay per step, against the oracle's run."""
+    to 50 FIRE updates, graph replays, against the oracle's run. Relaxations end
+    once the system has converged (chunks of RELAX_CHUNK_SINGLE iterations, launch
+    shapes tuned on the workload); the fixed sequence of 51 iterations per
+    relaxation is timed beside it."""
     import numpy as np
     import torch
 
@@ -370,15 +413,22 @@ def c0_leg():
     from paper_1910_01235_amd import mxe
     w = L.config0(0)
     s = w.systems[0]
-    plan = mxe.Plan([s], w.eam, w.params)
-    st, out, ws = plan.state([s]), plan.out(), plan.workspace()
-    plan.run(st, out, ws, 1, use_graph=True)  # records the graph on these buffers
-    torch.cuda.synchronize()
-    st0 = plan.state([s])  # back to the initial state, same buffers
-    for name in ("qx", "qy", "qz", "sigma", "x"):
-        getattr(st, name).copy_(getattr(st0, name))
-    out.scalars.zero_()
-    wall, sc, _ = timed_run(plan, st, out, ws, w.n_steps, use_graph=True, profile=False)
+    p_fast, shapes = tuned(w, "fp64", dict(w.params, relax_chunk=RELAX_CHUNK_SINGLE))
+
+    def one(params):
+        plan = mxe.Plan([s], w.eam, params)
+        st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+        plan.run(st, out, ws, 1, use_graph=True)  # records the graphs on these buffers
+        torch.cuda.synchronize()
+        st0 = plan.state([s])  # back to the initial state, same buffers
+        for name in ("qx", "qy", "qz", "sigma", "x"):
+            getattr(st, name).copy_(getattr(st0, name))
+        out.scalars.zero_()
+        wall, sc, _ = timed_run(plan, st, out, ws, w.n_steps, use_graph=True, profile=False)
+        return plan, st, out, wall, sc
+
+    wall_fixed = one(w.params)[3]
+    plan, st, out, wall, sc = one(p_fast)
     ev = int(sc[mxe.S_TOTAL_EVALS])
     t0 = time.perf_counter()
     r = O.run(w.eam, w.params, s.box, s.periodic, s.T, w.n_steps, s.q, s.sigma, s.x, s.type)
@@ -395,7 +445,9 @@ def c0_leg():
     return dict(workload=w.name, sites=s.n, steps=w.n_steps, max_relax=w.params["max_relax"],
                 wall_s=wall, value=s.n * ev / wall, unit="site-evals/s", evals=ev,
                 site_steps_per_s=s.n * w.n_steps / wall, ms_per_step=wall / w.n_steps * 1e3,
-                launch="one graph replay per diffusion step", status=int(sc[mxe.S_STATUS]),
+                launch=f"graph replays, relaxations in chunks of {RELAX_CHUNK_SINGLE} iterations ending "
+                       "once converged", launch_shapes=shapes, wall_s_fixed_sequence=wall_fixed,
+                status=int(sc[mxe.S_STATUS]),
                 oracle_wall_s=t_or, oracle_threads=O.num_threads(), error_vs_oracle=err)
 
 

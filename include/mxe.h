@@ -22,13 +22,16 @@
  *     entries. Systems never interact.
  *   Ownership: the caller allocates and owns every device buffer (state,
  *     outputs, workspace). The library never allocates device memory; a plan
- *     owns host memory, one HIP stream used only to record graphs, and the
- *     graphs it records. The one exception is mxe_run_noalloc's fixed scratch
+ *     owns host memory, one HIP stream used only to record graphs, the graphs
+ *     it records and, with params.relax_chunk > 0, 8 bytes of pinned host
+ *     memory and two events. The one exception is mxe_run_noalloc's fixed scratch
  *     array, held per device from the library's first use there until the
  *     process ends. All device pointers must be valid for the current HIP
  *     device.
  *   Asynchrony: every call only enqueues work on `stream` (a hipStream_t
- *     passed as void*, 0 = the null stream) and returns at once. Return codes
+ *     passed as void*, 0 = the null stream) and returns at once; with
+ *     params.relax_chunk > 0, mxe_relax and mxe_run wait on the host between
+ *     chunks of relaxation iterations while they enqueue. Return codes
  *     report argument and plan errors; errors the device detects are written
  *     to the per-system status scalar, to be read after the stream syncs.
  *   Determinism: no floating-point atomics; results are bitwise reproducible
@@ -128,6 +131,23 @@ typedef struct {
      * its neighbours one lattice layer away (25 for 40^3 FCC cells in lattice
      * order); performance only, results are bitwise the same for every S */
     int gather_stride;
+    /* relaxation schedule (performance only): 0 (default) enqueues every
+     * relaxation as its fixed max_relax + 1 FIRE iterations and returns at once
+     * (systems that have finished skip the rest). K > 0 (at most 1024) enqueues
+     * the iterations in chunks of K and, after each chunk, reads on the host how
+     * many systems are still relaxing; once none is, the relaxation ends after
+     * at most one more chunk (read one chunk behind, so the device never waits
+     * for the host). mxe_relax and mxe_run then block the calling thread while
+     * they enqueue (the work stays ordered on the caller's stream), and the
+     * first such call allocates 8 bytes of pinned host memory and two events
+     * that the plan keeps. Results are bitwise those of K = 0: an iteration
+     * after a system has finished changes nothing of it. */
+    int relax_chunk;
+    /* launch shape: pair-kernel blocks per chunk of 4096 pair slots (0 = 2; 1, 2,
+     * 4, 8 or 16). More blocks give small systems more parallel work at the
+     * cost of a pipeline prologue per block; performance only, results are
+     * bitwise the same for every value */
+    int pair_split;
 } mxe_params;
 
 typedef struct {
@@ -251,8 +271,9 @@ int64_t mxe_plan_sites(const mxe_plan* plan);
  * per-site array. mxe_plan_set_system rebinds a slot to another system of at
  * most that many sites (its first n_sites entries of the range; n_sites = 0
  * leaves the slot empty), with its own box, periodicity and temperature. The
- * change applies from the next call; launch shapes do not change, so recorded
- * graphs stay valid. Returns MXE_ERANGE if the system does not fit the slot
+ * change applies from the next call. Launches cover the occupied slots only
+ * (their chunks come first in the plan's tables; the extent is rounded up to a
+ * power of two), so many empty slots cost little. Returns MXE_ERANGE if the system does not fit the slot
  * (sites, or cells of its box), MXE_EINVAL for a bad box or temperature. A
  * system's results do not depend on its slot, its capacity or the other slots. */
 mxe_status mxe_plan_set_system(mxe_plan* plan, int slot, const mxe_system* sys);
@@ -293,7 +314,10 @@ mxe_status mxe_step(mxe_plan* plan, const mxe_state* state, const mxe_out* out, 
  * at fixed x, then one Euler step of x with mu of the last evaluation. Bonds
  * are built once at the start from the current positions. With use_graph != 0
  * the per-step launch sequence is recorded once into a HIP graph (per plan,
- * buffers and stream) and replayed. */
+ * buffers and launch extent; at most 16 are kept) and replayed; with
+ * params.relax_chunk > 0, one graph of
+ * relax_chunk iterations and one of the Euler step are recorded instead and
+ * each relaxation replays the first until every system has finished. */
 mxe_status mxe_run(mxe_plan* plan, const mxe_state* state, const mxe_out* out, int n_steps,
                    int use_graph, void* ws, size_t ws_bytes, void* stream);
 
@@ -309,7 +333,8 @@ mxe_status mxe_run(mxe_plan* plan, const mxe_state* state, const mxe_out* out, i
  * the state and outputs. The call allocates nothing (no hipMalloc, no
  * allocating library routine; its host-to-device copies of the plan's tables
  * come from host memory the plan owns).
- * Semantics: as mxe_run(use_graph = 0), except that every call starts afresh:
+ * Semantics: as mxe_run(use_graph = 0) with params.relax_chunk ignored (its
+ * early exit needs pinned host memory), except that every call starts afresh:
  * it uploads the plan's tables and rebuilds every neighbour list and bond
  * (resume mode is ignored), since other calls may have overwritten the scratch.
  * Results equal mxe_run's on a caller workspace.

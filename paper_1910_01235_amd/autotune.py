@@ -1,9 +1,10 @@
 """Launch-shape autotuner for the evaluation kernels.
 
-Four launch shapes change speed but not the method: the lanes per site of
+Five launch shapes change speed but not the method: the lanes per site of
 the density gather and of the force gather (8, 16, 32, 64 each), the block
-size of the pair quadrature kernel (64, 128, 256) and the gathers' chunk
-visit stride. The tuner times every candidate on the workload at hand (HIP
+size of the pair quadrature kernel (64, 128, 256) and its blocks per chunk of
+4096 pair slots (1 to 16: small systems want more, shorter blocks), and the
+gathers' chunk visit stride. The tuner times every candidate on the workload at hand (HIP
 events around each kernel launch, through the library's profiling switch),
 keeps the fastest of each, and caches the choice per size bucket, precision
 and lattice kind in a JSON file.
@@ -25,6 +26,8 @@ from . import mxe
 GATHER_LANES = (8, 16, 32, 64)
 CHUNK = 256  # sites per chunk of the gathers
 PAIR_BLOCKS = (64, 128, 256)
+PAIR_SPLITS = (1, 2, 4, 8, 16)
+SHAPES = ("gather_lanes", "force_lanes", "pair_block", "pair_split", "gather_stride")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mxe_autotune.json")
 
 
@@ -104,7 +107,8 @@ def stride_candidates(systems):
 
 def tune(systems, eam: dict, params: dict, precision: str = "fp64", reps: int = 5) -> dict:
     """Time every candidate shape on these systems; return the fastest and the timings."""
-    timings = {"gather_lanes": {}, "force_lanes": {}, "pair_block": {}, "gather_stride": {}}
+    timings = {"gather_lanes": {}, "force_lanes": {}, "pair_block": {}, "pair_split": {},
+               "gather_stride": {}}
     for g in GATHER_LANES:  # both gathers at once: each is timed on its own
         ms = _time_kernels(systems, eam, params, precision, reps, gather_lanes=g, force_lanes=g)
         timings["gather_lanes"][g] = ms["density"]
@@ -115,13 +119,17 @@ def tune(systems, eam: dict, params: dict, precision: str = "fp64", reps: int = 
     best_g = min(timings["gather_lanes"], key=timings["gather_lanes"].get)
     best_f = min(timings["force_lanes"], key=timings["force_lanes"].get)
     best_b = min(timings["pair_block"], key=timings["pair_block"].get)
+    for sp in PAIR_SPLITS:  # with the tuned block
+        ms = _time_kernels(systems, eam, params, precision, reps, pair_block=best_b, pair_split=sp)
+        timings["pair_split"][sp] = ms["pair"]
+    best_p = min(timings["pair_split"], key=timings["pair_split"].get)
     for st in stride_candidates(systems):  # with the tuned widths; both gathers together
         ms = _time_kernels(systems, eam, params, precision, reps, gather_lanes=best_g,
                            force_lanes=best_f, gather_stride=st)
         timings["gather_stride"][st] = ms["density"] + ms["force"]
     best_s = min(timings["gather_stride"], key=timings["gather_stride"].get)
     return dict(gather_lanes=int(best_g), force_lanes=int(best_f), pair_block=int(best_b),
-                gather_stride=int(best_s),
+                pair_split=int(best_p), gather_stride=int(best_s),
                 timings_ms={k: {str(a): round(b, 5) for a, b in v.items()} for k, v in timings.items()})
 
 
@@ -130,11 +138,10 @@ def tuned_params(systems, eam: dict, params: dict, precision: str = "fp64", cach
     """params with the tuned launch shapes (tuned now, or taken from the cache)."""
     key = bucket(systems, precision, int(params.get("quad_rule", eam.get("quad_rule", 0))))
     hit = None if (cache is None or retune) else cache.get(key)
-    if hit is not None and ("force_lanes" not in hit or "gather_stride" not in hit):
+    if hit is not None and any(k not in hit for k in SHAPES):
         hit = None  # written before these shapes existed
     if hit is None:
         hit = tune(systems, eam, params, precision, reps)
         if cache is not None:
             cache.put(key, hit)
-    return dict(params, gather_lanes=hit["gather_lanes"], force_lanes=hit["force_lanes"],
-                pair_block=hit["pair_block"], gather_stride=hit["gather_stride"]), hit
+    return dict(params, **{k: hit[k] for k in SHAPES}), hit

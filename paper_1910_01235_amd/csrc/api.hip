@@ -1,10 +1,13 @@
 // C ABI implementation: plans, workspace layout, launch sequences, graphs.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mxe_internal.h"
@@ -58,10 +61,21 @@ struct mxe_plan {
     size_t o_nbr, o_cnt, o_lo, o_pid, o_hoff, o_pi, o_pj, o_pnew, o_fblk, o_dblk, o_G, o_A, o_B;
     size_t o_v, o_qr, o_sref, o_emit, o_srec, o_bond, o_nbond, o_part, o_part_sub;
     size_t ws_bytes = 0;
-    // graph cache for mxe_run
+    // chunk tables hold the occupied slots' chunks first; launches cover that
+    // prefix (rounded up to a power of two)
+    int64_t live_chunks = 0, live_pchunks = 0;
+    // graph cache for mxe_run, per buffers and launch extents: one diffusion
+    // step, or (relax_chunk > 0) a chunk of relaxation iterations and the Euler step
+    struct Graphs {
+        hipGraphExec_t step = nullptr, chunk = nullptr, master = nullptr;
+    };
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph = nullptr;
-    std::vector<const void*> graph_key;
+    std::map<std::vector<const void*>, Graphs> graphs;
+    // early exit of chunked relaxations: systems still relaxing after a chunk,
+    // two slots of pinned host memory written by the device, and their events
+    int* act_host = nullptr;
+    int* act_dev = nullptr;
+    hipEvent_t act_ev[2] = {nullptr, nullptr};
     // profiling: event pairs bracketing launches, per kernel family
     bool prof_on = false;
     bool prof_pair_only = false;  // MXE_PROFILE_PAIR: only the pair kernel is bracketed
@@ -96,9 +110,48 @@ mxe_status slot_cells(const mxe_plan* P, const mxe_system& ms, int s, int64_t* n
     return MXE_OK;
 }
 
+// Chunk tables: the chunks of occupied slots first (in slot order), then those
+// of empty slots, so that launches can cover the occupied prefix alone. A
+// system's chunks stay contiguous and in site order from its chunk_first; no
+// result depends on which block or table position takes a chunk.
+void order_tables(mxe_plan* P) {
+    P->chunks.clear();
+    P->pchunks.clear();
+    P->live_chunks = P->live_pchunks = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int s = 0; s < P->n_sys; ++s) {
+            SysDesc& d = P->sys[s];
+            if ((d.n_sites > 0) != (pass == 0)) continue;
+            d.chunk_first = (int)P->chunks.size();
+            for (int c = 0; c < d.n_chunks; ++c) {
+                const int64_t a = (int64_t)c * kChunk;
+                P->chunks.push_back(Chunk{s, (int)(d.site_off + std::min<int64_t>(a, d.n_sites)),
+                                          (int)(d.site_off + std::min<int64_t>(a + kChunk, d.n_sites)), 0});
+            }
+            for (int64_t a = 0; a < d.pair_cap; a += kPairChunk)
+                P->pchunks.push_back(Chunk{s, (int)(d.pair_base + a),
+                                           (int)(d.pair_base + std::min<int64_t>(d.pair_cap, a + kPairChunk)), 0});
+            if (pass == 0) {
+                P->live_chunks = (int64_t)P->chunks.size();
+                P->live_pchunks = (int64_t)P->pchunks.size();
+            }
+        }
+}
+
+// Launch extent over a table whose first `live` entries are in use: the whole
+// table when all are, else `live` rounded up to a power of two (at least 64),
+// so that few distinct extents, and recorded graphs, occur.
+int launch_extent(int64_t live, int64_t total) {
+    if (live >= total) return (int)total;
+    int64_t e = 64;
+    while (e < live) e <<= 1;
+    return (int)std::min(e, total);
+}
+
 // Points slot s at system ms (n_sites <= capacity; 0 leaves the slot empty).
-// Offsets and capacities stay fixed, so recorded graphs remain valid.
-void bind_slot(mxe_plan* P, int s, const mxe_system& ms) {
+// Offsets and capacities stay fixed; the chunk tables are reordered (order:
+// false defers that to the caller).
+void bind_slot(mxe_plan* P, int s, const mxe_system& ms, bool order = true) {
     SysDesc& d = P->sys[s];
     d.n_sites = ms.n_sites;
     int64_t ncell = 1;
@@ -115,12 +168,6 @@ void bind_slot(mxe_plan* P, int s, const mxe_system& ms) {
     d.kT = kBoltzmannEv * ms.T;
     d.beta = 1.0 / d.kT;
     d.D = P->p.nu0 * std::exp(-d.beta * P->p.Qm);
-    for (int c = 0; c < d.n_chunks; ++c) {
-        const int64_t a = (int64_t)c * kChunk;
-        Chunk& ch = P->chunks[d.chunk_first + c];
-        ch.start = (int)(d.site_off + std::min<int64_t>(a, ms.n_sites));
-        ch.end = (int)(d.site_off + std::min<int64_t>(a + kChunk, ms.n_sites));
-    }
     P->systems[s] = ms;
     P->dirty[s] = 1;
     P->tables_dirty = true;
@@ -130,6 +177,7 @@ void bind_slot(mxe_plan* P, int s, const mxe_system& ms) {
         for (int64_t c = 0; c < P->sys[t].n_cells; ++c)
             P->acells.push_back(make_int2(t, (int)(P->sys[t].cell_off + c)));
     P->acells[0].x = (int)P->acells.size() - 1;
+    if (order) order_tables(P);
 }
 
 }  // namespace
@@ -226,6 +274,10 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
         return fail(MXE_EINVAL, "force_lanes must be 0, 8, 16, 32 or 64");
     if (p.gather_stride < 0 || p.gather_stride > 4096)
         return fail(MXE_EINVAL, "gather_stride must lie in [0, 4096]");
+    if (p.relax_chunk < 0 || p.relax_chunk > 1024) return fail(MXE_EINVAL, "relax_chunk must lie in [0, 1024]");
+    if (p.pair_split != 0 && p.pair_split != 1 && p.pair_split != 2 && p.pair_split != 4 && p.pair_split != 8 &&
+        p.pair_split != 16)
+        return fail(MXE_EINVAL, "pair_split must be 0, 1, 2, 4, 8 or 16");
     if (p.pair_block != 0 && p.pair_block != 64 && p.pair_block != 128 && p.pair_block != 256)
         return fail(MXE_EINVAL, "pair_block must be 0, 64, 128 or 256");
     if (p.quad_rule != MXE_QUAD_GH27 && p.quad_rule != MXE_QUAD_DEGREE3)
@@ -283,6 +335,8 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     m.force_lanes = p.force_lanes ? p.force_lanes : 16;
     m.gather_stride = p.gather_stride ? p.gather_stride : 1;
     m.pair_block = p.pair_block ? p.pair_block : 256;
+    m.pair_shift = 0;
+    while ((1 << m.pair_shift) < (p.pair_split ? p.pair_split : 2)) ++m.pair_shift;
     m.quad_rule = p.quad_rule;
     // near-minimax remainder polynomials of node_poly.h
     static_assert(sizeof(kExpE) == sizeof(m.poly.ex) && sizeof(kTaperS) == sizeof(m.poly.sn) &&
@@ -351,7 +405,8 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
         delete P;
         return fail(MXE_ERANGE, "plan too large for 32-bit indices");
     }
-    for (int s = 0; s < n_systems; ++s) bind_slot(P, s, systems[s]);
+    for (int s = 0; s < n_systems; ++s) bind_slot(P, s, systems[s], false);
+    order_tables(P);
 
     // workspace layout
     const size_t A = 256;
@@ -406,7 +461,12 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
 extern "C" void mxe_plan_destroy(mxe_plan* plan) {
     if (!plan) return;
     for (hipEvent_t e : plan->prof_events) (void)hipEventDestroy(e);
-    if (plan->graph) (void)hipGraphExecDestroy(plan->graph);
+    for (hipEvent_t e : plan->act_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (plan->act_host) (void)hipHostFree(plan->act_host);
+    for (auto& kv : plan->graphs)
+        for (hipGraphExec_t g : {kv.second.step, kv.second.chunk, kv.second.master})
+            if (g) (void)hipGraphExecDestroy(g);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
 }
@@ -502,8 +562,8 @@ mxe_status make_dev(const mxe_plan* P, const mxe_state* st, const mxe_out* out, 
     D.part_sub = (double*)(w + P->o_part_sub);
     D.n_sites = (int)N;
     D.n_sys = P->n_sys;
-    D.n_chunks = (int)P->chunks.size();
-    D.n_pchunks = (int)P->pchunks.size();
+    D.n_chunks = launch_extent(P->live_chunks, (int64_t)P->chunks.size());
+    D.n_pchunks = launch_extent(P->live_pchunks, (int64_t)P->pchunks.size());
     D.K = P->p.k_max;
     D.bond_max = P->p.bond_max;
     D.n_cells = P->n_cells;
@@ -623,6 +683,93 @@ void enqueue_diffusion_step(mxe_plan* P, const Dev& d, hipStream_t s) {
     timed(P, MXE_K_MASTER, s, [&] { launch_master(d, P->model, 0.0, s); }, true);
 }
 
+// Pinned host slots and events of the early exit, made on first use.
+mxe_status ensure_active_slots(mxe_plan* P) {
+    if (P->act_host) return MXE_OK;
+    int* h = nullptr;
+    HIP_OK(hipHostMalloc((void**)&h, 2 * sizeof(int), hipHostMallocMapped));
+    void* dp = nullptr;
+    hipError_t e = hipHostGetDevicePointer(&dp, h, 0);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&P->act_ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        for (hipEvent_t& ev : P->act_ev)
+            if (ev) {
+                (void)hipEventDestroy(ev);
+                ev = nullptr;
+            }
+        (void)hipHostFree(h);
+        return fail(MXE_EDEVICE, std::string("early-exit slots: ") + hipGetErrorString(e));
+    }
+    h[0] = h[1] = 1;
+    P->act_host = h;
+    P->act_dev = (int*)dp;
+    return MXE_OK;
+}
+
+// Waits (polling) for the event of a slot, then reads its count.
+mxe_status read_active(mxe_plan* P, int slot, int* active) {
+    for (;;) {
+        const hipError_t e = hipEventQuery(P->act_ev[slot]);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) return fail(MXE_EDEVICE, std::string("early-exit event: ") + hipGetErrorString(e));
+        std::this_thread::yield();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    *active = ((volatile int*)P->act_host)[slot];
+    return MXE_OK;
+}
+
+// A relaxation in chunks of relax_chunk iterations (one graph replay each, or
+// eager launches). After every chunk but the last, k_active writes how many
+// systems are still relaxing into a host slot; the host reads chunk c's count
+// after it has enqueued chunk c + 1, so the device never waits for the host,
+// and stops once the count is zero. The chunk enqueued meanwhile runs as a
+// no-op, as do the fixed sequence's iterations after a system has finished.
+mxe_status enqueue_relax_chunked(mxe_plan* P, const Dev& d, hipStream_t s, hipGraphExec_t graph) {
+    launch_relax_init(d, P->model, s);
+    P->prof_last = -1;
+    const int K = P->p.relax_chunk;
+    const int n_chunks = (P->p.max_relax + 1 + K - 1) / K;  // covers max_relax + 1 iterations
+    for (int c = 0; c < n_chunks; ++c) {
+        if (graph) {
+            HIP_OK(hipGraphLaunch(graph, s));
+        } else {
+            for (int k = 0; k < K; ++k) enqueue_iteration(P, d, s);
+        }
+        if (c + 1 < n_chunks) {
+            launch_active(d, P->act_dev + (c & 1), s);
+            P->prof_last = -1;  // an untimed launch breaks the chain
+            HIP_OK(hipEventRecord(P->act_ev[c & 1], s));
+        }
+        if (c >= 1) {
+            int active = 1;
+            const mxe_status r = read_active(P, (c - 1) & 1, &active);
+            if (r != MXE_OK) return r;
+            if (active == 0) break;
+        }
+    }
+    HIP_OK(hipGetLastError());
+    return MXE_OK;
+}
+
+// Records what `enqueue` launches on the plan's capture stream into *exec.
+template <typename F>
+mxe_status capture(mxe_plan* P, F&& enqueue, hipGraphExec_t* exec) {
+    if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
+    enqueue(P->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(P->cap_stream, &g);
+    if (e1 != hipSuccess) return fail(MXE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e1));
+    const hipError_t e2 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        *exec = nullptr;
+        return fail(MXE_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    }
+    return MXE_OK;
+}
+
 }  // namespace
 
 extern "C" mxe_status mxe_evaluate(mxe_plan* P, const mxe_state* st, const mxe_out* out, void* ws,
@@ -651,6 +798,11 @@ extern "C" mxe_status mxe_relax(mxe_plan* P, const mxe_state* st, const mxe_out*
     hipStream_t s = (hipStream_t)stream;
     r = begin_call(P, d, s, BUILD_LISTS);
     if (r != MXE_OK) return r;
+    if (P->p.relax_chunk > 0) {
+        r = ensure_active_slots(P);
+        if (r != MXE_OK) return r;
+        return enqueue_relax_chunked(P, d, s, nullptr);
+    }
     enqueue_relax(P, d, s);
     HIP_OK(hipGetLastError());
     return MXE_OK;
@@ -681,35 +833,57 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
     hipStream_t s = (hipStream_t)stream;
     r = begin_call(P, d, s, BUILD_LISTS_BONDS);
     if (r != MXE_OK) return r;
+    const bool chunked = P->p.relax_chunk > 0;
+    if (chunked) {
+        r = ensure_active_slots(P);
+        if (r != MXE_OK) return r;
+    }
     if (!use_graph || P->prof_on) {
-        for (int k = 0; k < n_steps; ++k) enqueue_diffusion_step(P, d, s);
+        for (int k = 0; k < n_steps; ++k) {
+            if (!chunked) {
+                enqueue_diffusion_step(P, d, s);
+                continue;
+            }
+            r = enqueue_relax_chunked(P, d, s, nullptr);
+            if (r != MXE_OK) return r;
+            timed(P, MXE_K_MASTER, s, [&] { launch_master(d, P->model, 0.0, s); });
+        }
         HIP_OK(hipGetLastError());
         return MXE_OK;
     }
-    std::vector<const void*> key = {st->qx, st->qy, st->qz, st->sigma, st->x, st->type,
-                                    st->reservoir, st->res_value, st->T_site, out->fx, out->fy,
-                                    out->fz, out->fsigma, out->mu, out->dxdt, out->rho_bar, out->rho0,
-                                    out->e_site, out->scalars, ws};
-    if (!P->graph || key != P->graph_key) {
-        if (P->graph) {
-            HIP_OK(hipGraphExecDestroy(P->graph));
-            P->graph = nullptr;
-        }
-        if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
-        HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
-        enqueue_diffusion_step(P, d, P->cap_stream);
-        hipGraph_t g = nullptr;
-        hipError_t e1 = hipStreamEndCapture(P->cap_stream, &g);
-        if (e1 != hipSuccess) return fail(MXE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e1));
-        hipError_t e2 = hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e2 != hipSuccess) {
-            P->graph = nullptr;
-            return fail(MXE_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
-        }
-        P->graph_key = key;
+    const std::vector<const void*> key = {st->qx, st->qy, st->qz, st->sigma, st->x, st->type,
+                                          st->reservoir, st->res_value, st->T_site, out->fx, out->fy,
+                                          out->fz, out->fsigma, out->mu, out->dxdt, out->rho_bar,
+                                          out->rho0, out->e_site, out->scalars, ws,
+                                          (const void*)(intptr_t)d.n_chunks, (const void*)(intptr_t)d.n_pchunks};
+    if (!P->graphs.count(key) && P->graphs.size() >= 16) {  // bounded cache: start afresh
+        for (auto& kv : P->graphs)
+            for (hipGraphExec_t g : {kv.second.step, kv.second.chunk, kv.second.master})
+                if (g) HIP_OK(hipGraphExecDestroy(g));
+        P->graphs.clear();
     }
-    for (int k = 0; k < n_steps; ++k) HIP_OK(hipGraphLaunch(P->graph, s));
+    mxe_plan::Graphs& G = P->graphs[key];
+    if (!chunked && !G.step) {
+        r = capture(P, [&](hipStream_t c) { enqueue_diffusion_step(P, d, c); }, &G.step);
+        if (r != MXE_OK) return r;
+    }
+    if (chunked && !G.master) {
+        r = capture(P, [&](hipStream_t c) {
+            for (int k = 0; k < P->p.relax_chunk; ++k) enqueue_iteration(P, d, c);
+        }, &G.chunk);
+        if (r != MXE_OK) return r;
+        r = capture(P, [&](hipStream_t c) { launch_master(d, P->model, 0.0, c); }, &G.master);
+        if (r != MXE_OK) return r;
+    }
+    for (int k = 0; k < n_steps; ++k) {
+        if (!chunked) {
+            HIP_OK(hipGraphLaunch(G.step, s));
+            continue;
+        }
+        r = enqueue_relax_chunked(P, d, s, G.chunk);
+        if (r != MXE_OK) return r;
+        HIP_OK(hipGraphLaunch(G.master, s));
+    }
     return MXE_OK;
 }
 

@@ -397,15 +397,15 @@ void k_pair(Dev d, Model m) {
     constexpr int kRow = per + 1;             // LDS row (odd stride against bank conflicts)
     // pair chunks are sized to capacity and only the leading ones are active,
     // so they keep the plain order (contiguous ranges per XCD would idle XCDs);
-    // kPairSplit blocks share a chunk, each taking a contiguous sub-range
-    const Chunk ch = d.pchunks[blockIdx.x / kPairSplit];
+    // 2^pair_shift blocks share a chunk, each taking a contiguous sub-range
+    const Chunk ch = d.pchunks[blockIdx.x >> m.pair_shift];
     const SysCtl& c = d.ctl[ch.sys];
     if (c.done) return;  // uniform over the block
     const SysDesc& S = d.sys[ch.sys];
-    constexpr int64_t kSub = kPairChunk / kPairSplit;
-    const int64_t cstart = ch.start + (int64_t)(blockIdx.x % kPairSplit) * kSub;
+    const int64_t sub = kPairChunk >> m.pair_shift;
+    const int64_t cstart = ch.start + (int64_t)(blockIdx.x & ((1u << m.pair_shift) - 1)) * sub;
     const int64_t pend =
-        min(min((int64_t)ch.end, cstart + kSub), S.pair_base + min((int64_t)c.n_pairs, S.pair_cap));
+        min(min((int64_t)ch.end, cstart + sub), S.pair_base + min((int64_t)c.n_pairs, S.pair_cap));
     Vec16<T>* fblk = (Vec16<T>*)d.fblk;
     T* dblk = (T*)d.dblk;
 
@@ -837,9 +837,9 @@ __global__ __launch_bounds__(kChunk) void k_force_fold(Dev d) {
 template <typename T, int kRule>
 void launch_pair_r(const Dev& d, const Model& m, int bs, hipStream_t s) {
     switch (bs) {
-        case 64: k_pair<T, 64, kRule><<<d.n_pchunks * kPairSplit, 64, 0, s>>>(d, m); break;
-        case 128: k_pair<T, 128, kRule><<<d.n_pchunks * kPairSplit, 128, 0, s>>>(d, m); break;
-        default: k_pair<T, 256, kRule><<<d.n_pchunks * kPairSplit, 256, 0, s>>>(d, m); break;
+        case 64: k_pair<T, 64, kRule><<<d.n_pchunks << m.pair_shift, 64, 0, s>>>(d, m); break;
+        case 128: k_pair<T, 128, kRule><<<d.n_pchunks << m.pair_shift, 128, 0, s>>>(d, m); break;
+        default: k_pair<T, 256, kRule><<<d.n_pchunks << m.pair_shift, 256, 0, s>>>(d, m); break;
     }
 }
 

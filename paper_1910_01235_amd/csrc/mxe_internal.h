@@ -12,7 +12,6 @@ constexpr int kFBlk = 16;           // force block per pair: 16 moments = one 12
 constexpr int kSRec = 8;            // per-site record: A~, B~, b, pair amplitude against A, B, S, 2 pad
 constexpr int kChunk = 256;         // sites per site-chunk; block size of per-site kernels
 constexpr int kPairChunk = 4096;    // pair slots per pair-chunk
-constexpr int kPairSplit = 2;       // pair-kernel blocks per pair-chunk (measured: 2 beats 1 and 4)
 constexpr int kNPart = 8;           // partial sums per site-chunk
 constexpr int kForceSplit = 8;      // force-gather blocks (and partial rows) per site chunk
 constexpr int kGatherSplit = 8;     // density-gather blocks per site chunk
@@ -98,6 +97,7 @@ struct Model {
     int quad_rule;                 // MXE_QUAD_GH27 or MXE_QUAD_DEGREE3
     PolyCoef poly;
     int gather_stride;             // chunk visit stride of the gathers (xcd_unit_strided)
+    int pair_shift;                // log2 of the pair-kernel blocks per pair chunk
 };
 
 // Every device pointer the kernels use.
@@ -286,6 +286,7 @@ void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s);
 void launch_force(const Dev& d, const Model& m, int precision, hipStream_t s);
 void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s);
 void launch_update(const Dev& d, const Model& m, hipStream_t s);
+void launch_active(const Dev& d, int* out, hipStream_t s);  // systems not done -> *out
 void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s);
 
 }  // namespace mxe

@@ -156,6 +156,28 @@ void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s) {
     k_control<<<d.n_sys, kChunk, 0, s>>>(d, m, mode);
 }
 
+// Number of systems still relaxing (not done), written by one block to *out
+// (a host-mapped int): the host reads it between chunks of iterations to end a
+// relaxation once every system has finished.
+__global__ __launch_bounds__(kChunk) void k_active(const SysCtl* ctl, int n_sys, int* out) {
+    __shared__ int lds[kChunk / kWave];
+    int n = 0;
+    for (int s = threadIdx.x; s < n_sys; s += blockDim.x) n += ctl[s].done ? 0 : 1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
+        *(volatile int*)out = t;
+    }
+}
+
+void launch_active(const Dev& d, int* out, hipStream_t s) {
+    k_active<<<1, kChunk, 0, s>>>(d.ctl, d.n_sys, out);
+}
+
 // FIRE velocity mixing and position/width update; records the largest
 // displacement and widening since the last build, from which the next build
 // decides whether the lists still hold.
@@ -268,8 +290,10 @@ __global__ __launch_bounds__(kChunk) void k_mstep_ctl(Dev d, Model m, double dt_
     __shared__ double lds[kChunk / kWave];
     const int s = blockIdx.x;
     const SysDesc& S = d.sys[s];
+    // an empty slot's chunks lie beyond the launched prefix: no rows, rate 0
+    const int nck = S.n_sites > 0 ? S.n_chunks : 0;
     double r = 0.0;
-    for (int k = threadIdx.x; k < S.n_chunks; k += blockDim.x)
+    for (int k = threadIdx.x; k < nck; k += blockDim.x)
         r = fmax(r, d.part[(int64_t)(S.chunk_first + k) * kNPart + P_RATE]);
     r = block_max(r, lds);
     if (threadIdx.x != 0) return;
@@ -313,8 +337,9 @@ __global__ __launch_bounds__(kChunk) void k_estep_ctl(Dev d) {
     __shared__ double lds[kChunk / kWave];
     const int s = blockIdx.x;
     const SysDesc& S = d.sys[s];
+    const int nck = S.n_sites > 0 ? S.n_chunks : 0;  // as in k_mstep_ctl
     double t = 0.0, r = 0.0;
-    for (int k = threadIdx.x; k < S.n_chunks; k += blockDim.x) {
+    for (int k = threadIdx.x; k < nck; k += blockDim.x) {
         t += d.part[(int64_t)(S.chunk_first + k) * kNPart + P_SUMX];
         r += d.part[(int64_t)(S.chunk_first + k) * kNPart + P_RES];
     }

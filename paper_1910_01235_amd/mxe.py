@@ -53,7 +53,8 @@ class Params(C.Structure):
                 ("skin", C.c_double), ("r_bond", C.c_double), ("k_max", C.c_int),
                 ("bond_max", C.c_int), ("precision", C.c_int), ("gather_lanes", C.c_int),
                 ("pair_block", C.c_int), ("quad_rule", C.c_int), ("force_lanes", C.c_int),
-                ("gather_stride", C.c_int)]
+                ("gather_stride", C.c_int), ("relax_chunk", C.c_int),
+                ("pair_split", C.c_int)]
 
 
 class System(C.Structure):
@@ -150,7 +151,8 @@ _PARAM_MAP = dict(nu0="nu0", Qm="Qm", kin_c="kin_c", dt_safety="dt_safety",
                   nmin="fire_nmin", sigma_min="sigma_min", r_bond="r_bond", sigma_cap="sigma_cap",
                   skin="skin", k_max="k_max", bond_max="bond_max", gather_lanes="gather_lanes",
                   pair_block="pair_block", quad_rule="quad_rule", force_lanes="force_lanes",
-                  gather_stride="gather_stride")
+                  gather_stride="gather_stride", relax_chunk="relax_chunk",
+                  pair_split="pair_split")
 
 
 def make_params(params: dict, precision: str = "fp64", **over) -> Params:

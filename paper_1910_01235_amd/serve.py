@@ -238,9 +238,11 @@ class Server:
 
 
 def serve_one_at_a_time(eam: dict, params: dict, requests: list, precision: str = "fp64",
-                        realtime: bool = True, device: str = "cuda", progress=None):
+                        realtime: bool = True, device: str = "cuda", progress=None, params_for=None):
     """The plain path: each request alone on its own plan, in arrival order.
-    progress: optional callable, given the number of requests done after each."""
+    progress: optional callable, given the number of requests done after each.
+    params_for: optional callable giving the parameters for one system (e.g.
+    launch shapes tuned for its size); default: params for every request."""
     import torch
     results = []
     pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -250,7 +252,8 @@ def serve_one_at_a_time(eam: dict, params: dict, requests: list, precision: str 
         if realtime and r.arrival > now():
             time.sleep(r.arrival - now())
         ta = now()
-        plan = mxe.Plan([r.system], eam, params, precision=precision)
+        plan = mxe.Plan([r.system], eam, params_for(r.system) if params_for else params,
+                        precision=precision)
         st, out, ws = plan.state([r.system], device), plan.out(device), plan.workspace(device)
         plan.run(st, out, ws, r.n_steps, use_graph=True)
         torch.cuda.synchronize()

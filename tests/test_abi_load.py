@@ -60,6 +60,11 @@ def test_plan_validation_needs_no_gpu():
     with pytest.raises(mxe.MxeError, match="bond_max"):
         mxe.Plan(w.systems, w.eam, dict(w.params, bond_max=65))
     assert mxe.Plan(w.systems, w.eam, dict(w.params, bond_max=64)).n_sites == 256
+    # the relaxation chunk is bounded; creating a chunked plan touches no device
+    for bad in (-1, 1025):
+        with pytest.raises(mxe.MxeError, match="relax_chunk"):
+            mxe.Plan(w.systems, w.eam, dict(w.params, relax_chunk=bad))
+    assert mxe.Plan(w.systems, w.eam, dict(w.params, relax_chunk=4)).params.relax_chunk == 4
     # fp32 workspace is smaller (FP32 moments)
     p32 = mxe.Plan(w.systems, w.eam, w.params, precision="fp32")
     assert p32.ws_bytes < plan.ws_bytes

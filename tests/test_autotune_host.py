@@ -41,6 +41,11 @@ def test_plan_validates_launch_shapes():
         mxe.Plan(w.systems, w.eam, w.params, gather_stride=st)
     with pytest.raises(mxe.MxeError, match="gather_stride"):
         mxe.Plan(w.systems, w.eam, w.params, gather_stride=-1)
+    for sp in autotune.PAIR_SPLITS:
+        mxe.Plan(w.systems, w.eam, w.params, pair_split=sp)
+    for bad in (3, 32, -1):
+        with pytest.raises(mxe.MxeError, match="pair_split"):
+            mxe.Plan(w.systems, w.eam, w.params, pair_split=bad)
 
 
 def test_layer_stride_from_site_order():

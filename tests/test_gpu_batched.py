@@ -155,19 +155,24 @@ def test_autotuned_shapes_keep_results(mx, tmp_path):
     assert params["pair_block"] in autotune.PAIR_BLOCKS
     assert cache.get(autotune.bucket([s], "fp64", 0)) == hit
     assert params["gather_stride"] >= 1
+    assert params["pair_split"] in autotune.PAIR_SPLITS
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_gather_stride_keeps_results_bitwise(mx, precision):
-    """The gathers' chunk visit order changes no sum: every stride gives the same bits,
-    on one multi-chunk system and on a batch whose systems straddle XCD ranges."""
+def test_gather_stride_and_pair_split_keep_results_bitwise(mx, precision):
+    """The gathers' chunk visit order changes no sum, and which pair-kernel block
+    takes a pair changes none of its moments: every stride and every split gives
+    the same bits, on one multi-chunk system and on a batch whose systems
+    straddle XCD ranges."""
     one = [L.jitter(L.vacancy_bulk(8, 6, 900.0, 5), 7, xr=(0.3, 0.9))]  # 2048 sites, 8 chunks
     batch = _mixed_systems() + [L.vacancy_bulk(9, 2, 800.0, 9)]
     p = dict(L.DEFAULT_PARAMS, max_relax=4)
     for systems in (one, batch):
         ref = None
-        for stride in (1, 2, 3, 7, 26, 4096):
-            plan = mx.Plan(systems, L.DEFAULT_EAM, p, precision=precision, gather_stride=stride)
+        shapes = [dict(gather_stride=st) for st in (1, 2, 3, 7, 26, 4096)] + \
+                 [dict(pair_split=sp, pair_block=b) for sp in (1, 4, 8, 16) for b in (64, 256)]
+        for shape in shapes:
+            plan = mx.Plan(systems, L.DEFAULT_EAM, p, precision=precision, **shape)
             st, out, ws = plan.state(systems), plan.out(), plan.workspace()
             plan.run(st, out, ws, 2, use_graph=False)
             torch.cuda.synchronize()
@@ -177,5 +182,5 @@ def test_gather_stride_keeps_results_bitwise(mx, precision):
             if ref is None:
                 ref = got
             for a, b in zip(got, ref):
-                assert np.array_equal(a, b), (precision, len(systems), stride)
+                assert np.array_equal(a, b), (precision, len(systems), shape)
 
