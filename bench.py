@@ -50,16 +50,16 @@ BREAKDOWN_STEPS = 2
 
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
 # this bench (--steps 2 --warmup 1 --no-extras --no-cpu-baseline --calib-copy
-# --shapes gather_lanes=8,force_lanes=16,pair_block=256,gather_stride=26),
+# --shapes gather_lanes=8,force_lanes=16,pair_block=256,pair_split=8,gather_stride=26),
 # KiB per dispatch averaged over the run's dispatches, scaled by what the same
 # counters read for a 1 GiB device copy (FETCH x 2, WRITE x 1). Valid only for
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="9e6c48511664837a",
-    pair=dict(fetch_kib=160083.9, write_kib=1019787.0),
-    force=dict(fetch_kib=896910.9, write_kib=13688.5),
-    density=dict(fetch_kib=137353.4, write_kib=27090.6),
+    sources_sha256_16="db0d119be0145a6d",
+    pair=dict(fetch_kib=70720.2, write_kib=1019787.0),
+    force=dict(fetch_kib=896904.3, write_kib=13679.7),
+    density=dict(fetch_kib=137313.7, write_kib=27103.9),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -78,11 +78,11 @@ def counter_traffic(family: str):
 # VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
 # Valid only for the sources they were taken on.
 VALU_COUNTERS = dict(
-    sources_sha256_16="9e6c48511664837a",
-    pair=dict(SQ_INSTS_VALU=223472590.2, SQ_INSTS_VALU_FMA_F64=121838857.9,
-              SQ_INSTS_VALU_MUL_F64=29486458.4, SQ_INSTS_VALU_ADD_F64=12554676.0,
-              SQ_INSTS_VALU_TRANS_F64=3222591.1, SQ_INSTS_VALU_FLOPS_FP64=288942441.8,
-              VALUBusy=74.81, VALUUtilization=90.39),
+    sources_sha256_16="db0d119be0145a6d",
+    pair=dict(SQ_INSTS_VALU=226717400.6, SQ_INSTS_VALU_FMA_F64=121838355.2,
+              SQ_INSTS_VALU_MUL_F64=29613842.6, SQ_INSTS_VALU_ADD_F64=12554670.2,
+              SQ_INSTS_VALU_TRANS_F64=3222592.0, SQ_INSTS_VALU_FLOPS_FP64=289069849.9,
+              VALUBusy=71.30, VALUUtilization=90.37),
 )
 
 
