@@ -353,12 +353,13 @@ def timed_run(plan, st, out, ws, steps, use_graph, profile):
     return wall, sc, prof
 
 
-def tuned(w, precision, params=None):
+def tuned(w, precision, params=None, quad_rule=0):
     """The workload's parameters with the autotuner's launch shapes (tuned on this
-    GPU, or read from the tuner's cache) and the shapes chosen."""
+    GPU for this precision and rule, or read from the tuner's cache) and the
+    shapes chosen."""
     from paper_1910_01235_amd import autotune
-    p, hit = autotune.tuned_params(w.systems, w.eam, params or w.params, precision=precision,
-                                   cache=autotune.Cache(), reps=3)
+    p, hit = autotune.tuned_params(w.systems, dict(w.eam, quad_rule=quad_rule), params or w.params,
+                                   precision=precision, cache=autotune.Cache(), reps=3)
     return p, {k: hit[k] for k in autotune.SHAPES}
 
 
@@ -374,7 +375,7 @@ def fullsize_leg(w, precision, steps, warmup, quad_rule=0, params=None):
     s = w.systems[0]
     eam = dict(w.eam, quad_rule=quad_rule)
     if params is None:
-        params, shapes = tuned(w, precision)
+        params, shapes = tuned(w, precision, quad_rule=quad_rule)
     else:
         from paper_1910_01235_amd import autotune
         shapes = {k: params.get(k) for k in autotune.SHAPES}
@@ -598,15 +599,18 @@ def main():
         log(f"graph leg: {wall_g:.3f} s")
     del st, out, ws, plan
     torch.cuda.empty_cache()
+    # the other legs on this workload: tuned for their own precision and rule,
+    # unless --shapes fixes the shapes for every leg
+    leg_params = params if args.shapes else None
     if "fp32" in legs:
-        result["fp32_mixed"] = fullsize_leg(w, "fp32", args.steps, args.warmup, params=params)
+        result["fp32_mixed"] = fullsize_leg(w, "fp32", args.steps, args.warmup, params=leg_params)
         log(f"fp32 leg: {result['fp32_mixed']['value']:.4g} site-evals/s")
     if "degree3" in legs:
         # the paper's own degree-3 rule (12 nodes in the pair's 6-D space)
         result["degree3"] = {}
         for prec in ("fp64", "fp32"):
             result["degree3"][prec] = fullsize_leg(w, prec, args.steps, args.warmup, quad_rule=1,
-                                                   params=params)
+                                                   params=leg_params)
             log(f"degree-3 {prec} leg: {result['degree3'][prec]['value']:.4g} site-evals/s")
     if "variants" in legs:
         # state variants on the same workload: site temperatures, reservoir sites
