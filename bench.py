@@ -199,6 +199,7 @@ def sampled_errors(workload, plan, st, out, ws, precision, n_sample=64, seed=0):
 
 RELAX_CHUNK_BATCHED = 4   # relaxation chunk of the batched plan and the server pool
 RELAX_CHUNK_SINGLE = 2    # and of the one-at-a-time path (small systems, short chunks)
+ADVANCE_ITERS = 8         # iterations per call of the iteration-level server
 
 
 def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
@@ -218,7 +219,10 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
     converged (relax_chunk > 0; the one-at-a-time path with launch shapes tuned
     per size octave), and the fixed sequence of max_relax + 1 iterations per
     relaxation with the batch's shapes everywhere (`fixed_sequence`, at the
-    same absolute arrival rates for before_rates)."""
+    same absolute arrival rates for before_rates). The server runs at the
+    iteration level (free-running steps, `served`) and, for before_rates, at
+    the step level (`served_step_level`: one diffusion step of every resident
+    system per call)."""
     import numpy as np
     import torch
 
@@ -242,6 +246,12 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
         single[id(s)] = p1
     octaves = {k: {kk: v[kk] for kk in autotune.SHAPES} for k, v in sorted(cache.data.items())}
     log(f"serving: shapes per size octave {octaves}")
+    # the server's pool mostly holds a few systems at a time: its shapes are
+    # tuned on eight requests spread over the size range
+    sample = sorted(systems, key=lambda t: t.n)[::len(systems) // 8][:8]
+    params_pool, tuned_pool = autotune.tuned_params(sample, L.DEFAULT_EAM, base, cache=None, reps=2)
+    shapes_pool = {k: tuned_pool[k] for k in autotune.SHAPES}
+    log(f"serving: pool shapes {shapes_pool}")
 
     def batched(p):
         torch.cuda.synchronize()
@@ -282,10 +292,11 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
         return dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                     systems_per_s=len(lat) / c)
 
-    def served(p, rates, service, tag):
+    def served(p, rates, service, tag, iteration_level=False):
         per_site = serve.bytes_per_site(L.DEFAULT_EAM, p)
         caps = serve.pool_capacities(budget_gb * 1e9, per_site)
-        srv = serve.Server(L.DEFAULT_EAM, p, caps)
+        srv = serve.Server(L.DEFAULT_EAM, p, caps, iteration_level=iteration_level,
+                           advance_iters=ADVANCE_ITERS)
         warm = serve.poisson_requests([L.vacancy_bulk(5, 1, 800.0, 0)], n_steps=1, rate=0.0)
         srv.serve(warm, realtime=False)  # records the step graphs
         rows = []
@@ -313,7 +324,10 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
     cap = bat["systems_per_s"]
     log(f"serving: batched {bat['wall_s']:.1f} s, {cap:.1f} systems/s")
     one, service, res1 = one_at_a_time(params, lambda s: single[id(s)], "early exit")
-    srv_rows, n_slots, fp = served(p_b, [(f, f * cap) for f in rate_factors], service, "early exit")
+    p_pool = dict(params_pool, relax_chunk=RELAX_CHUNK_BATCHED)
+    srv_rows, n_slots, fp = served(p_pool, [(f, f * cap) for f in rate_factors], service,
+                                   "iteration level", iteration_level=True)
+    srv_step, _, _ = served(p_pool, [(f, f * cap) for f in before_rates], service, "step level")
     # fixed sequence, same absolute arrival rates
     bat0, x_b0 = batched(params)
     log(f"serving: batched, fixed sequence {bat0['wall_s']:.1f} s")
@@ -326,10 +340,13 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
                                                             sorted(res0, key=lambda r: r.rid)))
     return dict(requests=len(systems), sites=n_tot, steps_per_request=n_steps,
                 max_relax=params["max_relax"], shapes=shapes, shapes_one_at_a_time=octaves,
+                shapes_server=shapes_pool,
                 relax_chunk=dict(batched=RELAX_CHUNK_BATCHED, served=RELAX_CHUNK_BATCHED,
                                  one_at_a_time=RELAX_CHUNK_SINGLE),
                 batched=bat, one_at_a_time=one, batched_vs_one_at_a_time=cap / one["systems_per_s"],
-                served=srv_rows, slots=n_slots, footprint_gb=fp,
+                served=srv_rows, server="iteration level: free-running steps, "
+                f"calls of {ADVANCE_ITERS} iterations", served_step_level=srv_step,
+                slots=n_slots, footprint_gb=fp,
                 fixed_sequence=dict(batched=bat0, one_at_a_time=one0, served=srv0,
                                     batched_x_bitwise_equal=bool(same),
                                     one_at_a_time_max_abs_dx=dx))

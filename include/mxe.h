@@ -224,6 +224,8 @@ typedef enum {
     MXE_S_PAIR_EVALS = 12, /* pair quadratures during the call                  */
     MXE_S_RESERVOIR = 13, /* matter taken up by held-x sites; in/out, accumulated
                            * like MXE_S_TIME: sum x + this stays constant      */
+    MXE_S_STEPS_LEFT = 14, /* mxe_advance: diffusion steps the system still has
+                            * to run (0: its budget is spent)                   */
     MXE_NSCALARS = 16
 } mxe_scalar;
 
@@ -320,6 +322,33 @@ mxe_status mxe_step(mxe_plan* plan, const mxe_state* state, const mxe_out* out, 
  * each relaxation replays the first until every system has finished. */
 mxe_status mxe_run(mxe_plan* plan, const mxe_state* state, const mxe_out* out, int n_steps,
                    int use_graph, void* ws, size_t ws_bytes, void* stream);
+
+/* Free-running steps (Sec. 4, Alg. 1, per system): every system with steps
+ * left relaxes at fixed x; when its relaxation ends (converged or max_relax
+ * updates) its Euler step follows in the same iteration and, if steps remain,
+ * its next relaxation starts with the next iteration, whatever the other
+ * systems are doing. Each system runs exactly the relaxations and steps it
+ * would run alone under mxe_run, so its results equal those bitwise; only
+ * systems stop waiting for each other at step boundaries (continuous batching
+ * of requests, one iteration at a time).
+ *   mxe_plan_set_steps gives a slot a budget of n_steps diffusion steps from
+ *   the next mxe_advance on: its counters and scalars restart, a fresh
+ *   relaxation begins, and MXE_S_STEPS_LEFT counts down to 0. A slot never
+ *   given a budget has none.
+ *   mxe_advance enqueues up to max_iters iterations, in chunks of
+ *   params.relax_chunk (required > 0), and stops early once no system has
+ *   steps left (read on the host one chunk behind; the call waits on the host
+ *   between chunks). Systems keep their relaxation state, counters and budget
+ *   across calls, so a later call continues where this one stopped. Resume
+ *   mode is required (slots rebound since the last call rebuild their lists
+ *   and bonds; bonds are built when a slot is bound and kept after). With
+ *   use_graph != 0 a chunk of iterations is recorded once per buffers and
+ *   launch extent and replayed.
+ * Errors: MXE_EINVAL for relax_chunk <= 0, resume mode off, max_iters < 0, a
+ * slot out of range or n_steps < 0. */
+mxe_status mxe_plan_set_steps(mxe_plan* plan, int slot, int n_steps);
+mxe_status mxe_advance(mxe_plan* plan, const mxe_state* state, const mxe_out* out, int max_iters,
+                       int use_graph, void* ws, size_t ws_bytes, void* stream);
 
 /* Size of the device scratch that mxe_run_noalloc uses instead of a workspace:
  * one array per device, held from the library's first use on that device

@@ -44,6 +44,7 @@ struct mxe_plan {
     std::vector<int64_t> cap_sites, cap_cells;  // slot capacities
     double r_cap = 0.0, r_cell = 0.0;
     std::vector<char> dirty;     // slot rebound since the last call
+    std::vector<int> steps_new;  // mxe_advance budgets to apply at the next call (-1: keep)
     bool resume = false;         // calls rebuild only dirty slots
     bool tables_dirty = true;    // chunk tables changed since the last upload
     void* tables_ws = nullptr;   // workspace that holds the uploaded tables
@@ -67,7 +68,7 @@ struct mxe_plan {
     // graph cache for mxe_run, per buffers and launch extents: one diffusion
     // step, or (relax_chunk > 0) a chunk of relaxation iterations and the Euler step
     struct Graphs {
-        hipGraphExec_t step = nullptr, chunk = nullptr, master = nullptr;
+        hipGraphExec_t step = nullptr, chunk = nullptr, master = nullptr, advance = nullptr;
     };
     hipStream_t cap_stream = nullptr;
     std::map<std::vector<const void*>, Graphs> graphs;
@@ -362,6 +363,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     int64_t site_off = 0, cell_off = 0, pair_base = 0;
     P->sys.resize(n_systems);
     P->dirty.assign(n_systems, 1);
+    P->steps_new.assign(n_systems, 0);
     P->cap_sites.resize(n_systems);
     P->cap_cells.resize(n_systems);
     for (int s = 0; s < n_systems; ++s) {
@@ -465,7 +467,7 @@ extern "C" void mxe_plan_destroy(mxe_plan* plan) {
         if (e) (void)hipEventDestroy(e);
     if (plan->act_host) (void)hipHostFree(plan->act_host);
     for (auto& kv : plan->graphs)
-        for (hipGraphExec_t g : {kv.second.step, kv.second.chunk, kv.second.master})
+        for (hipGraphExec_t g : {kv.second.step, kv.second.chunk, kv.second.master, kv.second.advance})
             if (g) (void)hipGraphExecDestroy(g);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
@@ -580,15 +582,21 @@ enum CallBuild { BUILD_LISTS, BUILD_LISTS_BONDS, BUILD_BONDS };
 // they changed or the workspace differs, the chunk tables; then initialises
 // the call and builds the lists of every system that must be rebuilt (and the
 // bonds), or only the bonds.
-mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, CallBuild what) {
+mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, CallBuild what, bool advance = false) {
     P->prof_last = -1;  // the untimed launches below break the profiling chain
     const bool lists = what != BUILD_BONDS;
     // a workspace the plan has not built lists in holds none: build everything
     const bool new_ws = P->tables_ws != (void*)d.sys;
     const bool new_lists = P->lists_ws != (void*)d.sys;
-    for (int k = 0; k < P->n_sys; ++k)
+    for (int k = 0; k < P->n_sys; ++k) {
         P->sys[k].force_build = (lists && (!P->resume || new_lists || P->dirty[k])) ? 1 : 0;
+        // free-running budgets: a workspace new to the plan holds none
+        int sn = advance ? P->steps_new[k] : -1;
+        if (advance && new_lists && sn < 0) sn = 0;
+        P->sys[k].steps_new = sn;
+    }
     HIP_OK(hipMemcpyAsync(d.sys, P->sys.data(), sizeof(SysDesc) * P->sys.size(), hipMemcpyHostToDevice, s));
+    if (advance) std::fill(P->steps_new.begin(), P->steps_new.end(), -1);
     if (P->tables_dirty || new_ws) {
         HIP_OK(hipMemcpyAsync(d.chunks, P->chunks.data(), sizeof(Chunk) * P->chunks.size(),
                               hipMemcpyHostToDevice, s));
@@ -600,7 +608,7 @@ mxe_status begin_call(mxe_plan* P, const Dev& d, hipStream_t s, CallBuild what) 
         P->tables_ws = (void*)d.sys;
     }
     launch_ws_init(d, s);
-    launch_sys_init(d, P->model, s);
+    launch_sys_init(d, P->model, s, advance ? 1 : 0);
     if (lists) {
         std::fill(P->dirty.begin(), P->dirty.end(), 0);
         P->lists_ws = (void*)d.sys;
@@ -663,13 +671,16 @@ void enqueue_eval(mxe_plan* P, const Dev& d, hipStream_t s) {
     timed(P, MXE_K_FORCE, s, [&] { launch_force(d, P->model, prec, s); }, true);
 }
 
-void enqueue_iteration(mxe_plan* P, const Dev& d, hipStream_t s) {
+// One relaxation iteration; free_run (mxe_advance) also takes the Euler step
+// of every system whose relaxation ended in it.
+void enqueue_iteration(mxe_plan* P, const Dev& d, hipStream_t s, bool free_run = false) {
     timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, false, s); }, true);
     enqueue_eval(P, d, s);
     timed(P, MXE_K_FIRE, s, [&] {
-        launch_control(d, P->model, 1, s);
+        launch_control(d, P->model, free_run ? 2 : 1, s);
         launch_update(d, P->model, s);
     }, true);
+    if (free_run) timed(P, MXE_K_MASTER, s, [&] { launch_master(d, P->model, 0.0, s, 1); }, true);
 }
 
 void enqueue_relax(mxe_plan* P, const Dev& d, hipStream_t s) {
@@ -737,7 +748,7 @@ mxe_status enqueue_relax_chunked(mxe_plan* P, const Dev& d, hipStream_t s, hipGr
             for (int k = 0; k < K; ++k) enqueue_iteration(P, d, s);
         }
         if (c + 1 < n_chunks) {
-            launch_active(d, P->act_dev + (c & 1), s);
+            launch_active(d, P->act_dev + (c & 1), 0, s);
             P->prof_last = -1;  // an untimed launch breaks the chain
             HIP_OK(hipEventRecord(P->act_ev[c & 1], s));
         }
@@ -858,7 +869,7 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
                                           (const void*)(intptr_t)d.n_chunks, (const void*)(intptr_t)d.n_pchunks};
     if (!P->graphs.count(key) && P->graphs.size() >= 16) {  // bounded cache: start afresh
         for (auto& kv : P->graphs)
-            for (hipGraphExec_t g : {kv.second.step, kv.second.chunk, kv.second.master})
+            for (hipGraphExec_t g : {kv.second.step, kv.second.chunk, kv.second.master, kv.second.advance})
                 if (g) HIP_OK(hipGraphExecDestroy(g));
         P->graphs.clear();
     }
@@ -884,6 +895,77 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
         if (r != MXE_OK) return r;
         HIP_OK(hipGraphLaunch(G.master, s));
     }
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_plan_set_steps(mxe_plan* P, int slot, int n_steps) {
+    if (!P) return fail(MXE_EINVAL, "null plan");
+    if (slot < 0 || slot >= P->n_sys) return fail(MXE_EINVAL, "slot out of range");
+    if (n_steps < 0) return fail(MXE_EINVAL, "n_steps < 0");
+    P->steps_new[slot] = n_steps;
+    return MXE_OK;
+}
+
+extern "C" mxe_status mxe_advance(mxe_plan* P, const mxe_state* st, const mxe_out* out, int max_iters,
+                                  int use_graph, void* ws, size_t ws_bytes, void* stream) {
+    if (!P) return fail(MXE_EINVAL, "null plan");
+    if (max_iters < 0) return fail(MXE_EINVAL, "max_iters < 0");
+    if (P->p.relax_chunk <= 0) return fail(MXE_EINVAL, "mxe_advance needs params.relax_chunk > 0");
+    if (!P->resume) return fail(MXE_EINVAL, "mxe_advance needs resume mode (mxe_plan_set_resume)");
+    Dev d;
+    mxe_status r = make_dev(P, st, out, ws, ws_bytes, &d);
+    if (r != MXE_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    r = ensure_active_slots(P);
+    if (r != MXE_OK) return r;
+    r = begin_call(P, d, s, BUILD_LISTS_BONDS, true);
+    if (r != MXE_OK) return r;
+    const int K = P->p.relax_chunk;
+    hipGraphExec_t g = nullptr;
+    if (use_graph && !P->prof_on) {
+        const std::vector<const void*> key = {st->qx, st->qy, st->qz, st->sigma, st->x, st->type,
+                                              st->reservoir, st->res_value, st->T_site, out->fx, out->fy,
+                                              out->fz, out->fsigma, out->mu, out->dxdt, out->rho_bar,
+                                              out->rho0, out->e_site, out->scalars, ws,
+                                              (const void*)(intptr_t)d.n_chunks,
+                                              (const void*)(intptr_t)d.n_pchunks};
+        if (!P->graphs.count(key) && P->graphs.size() >= 16) {  // bounded cache: start afresh
+            for (auto& kv : P->graphs)
+                for (hipGraphExec_t e : {kv.second.step, kv.second.chunk, kv.second.master, kv.second.advance})
+                    if (e) HIP_OK(hipGraphExecDestroy(e));
+            P->graphs.clear();
+        }
+        mxe_plan::Graphs& G = P->graphs[key];
+        if (!G.advance) {
+            r = capture(P, [&](hipStream_t c) {
+                for (int k = 0; k < K; ++k) enqueue_iteration(P, d, c, true);
+            }, &G.advance);
+            if (r != MXE_OK) return r;
+        }
+        g = G.advance;
+    }
+    // chunks of K free-running iterations until no system has steps left (read
+    // one chunk behind, as in enqueue_relax_chunked) or max_iters are enqueued
+    const int n_chunks = (max_iters + K - 1) / K;
+    for (int c = 0; c < n_chunks; ++c) {
+        if (g) {
+            HIP_OK(hipGraphLaunch(g, s));
+        } else {
+            for (int k = 0; k < K; ++k) enqueue_iteration(P, d, s, true);
+        }
+        if (c + 1 < n_chunks) {
+            launch_active(d, P->act_dev + (c & 1), 1, s);
+            P->prof_last = -1;
+            HIP_OK(hipEventRecord(P->act_ev[c & 1], s));
+        }
+        if (c >= 1) {
+            int active = 1;
+            r = read_active(P, (c - 1) & 1, &active);
+            if (r != MXE_OK) return r;
+            if (active == 0) break;
+        }
+    }
+    HIP_OK(hipGetLastError());
     return MXE_OK;
 }
 

@@ -43,7 +43,7 @@ struct SysDesc {
     double T, kT, beta, D;  // reference temperature and its derived constants
     int chunk_first, n_chunks;
     int force_build;  // rebuild lists and bonds at the start of the call
-    int pad;
+    int steps_new;    // mxe_advance: a new step budget from this call on, or -1
 };
 
 struct SysCtl {
@@ -58,6 +58,9 @@ struct SysCtl {
     double pair_evals;
     int n_pairs;
     int status;
+    // free-running steps (mxe_advance): diffusion steps still to run, and the
+    // flag that the relaxation ended in this iteration (its Euler step follows)
+    int steps_left, stepping;
     int pad;
 };
 
@@ -274,7 +277,7 @@ __device__ inline double wave_sum(double v) {
 // Host-side launchers (each defined next to its kernels).
 // ---------------------------------------------------------------------------
 void launch_ws_init(const Dev& d, hipStream_t s);
-void launch_sys_init(const Dev& d, const Model& m, hipStream_t s);
+void launch_sys_init(const Dev& d, const Model& m, hipStream_t s, int advance = 0);
 // bonds: also rebuild the bond lists; finish: count the build and clear the
 // request at the end of the chain (otherwise the next k_control does it)
 void launch_build(const Dev& d, const Model& m, bool bonds, bool finish, hipStream_t s);
@@ -286,7 +289,20 @@ void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s);
 void launch_force(const Dev& d, const Model& m, int precision, hipStream_t s);
 void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s);
 void launch_update(const Dev& d, const Model& m, hipStream_t s);
-void launch_active(const Dev& d, int* out, hipStream_t s);  // systems not done -> *out
-void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s);
+// systems not done (steps = 0) or with diffusion steps left (steps = 1) -> *out
+void launch_active(const Dev& d, int* out, int steps, hipStream_t s);
+// free_run: only systems whose relaxation ended in this iteration step
+void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s, int free_run = 0);
+// relaxation state at the start of a relaxation (FIRE scalars and counters)
+__device__ inline void relax_start(SysCtl& c, const Model& m) {
+    c.fire_dt = m.dt0;
+    c.fire_alpha = m.alpha0;
+    c.npos = 0;
+    c.k = 0;
+    c.done = 0;
+    c.converged = 0;
+    c.updates = 0;
+    c.evals = 0;
+}
 
 }  // namespace mxe

@@ -80,25 +80,38 @@ void launch_ws_init(const Dev& d, hipStream_t s) {
     k_zero_int<<<(d.n_chunks + 255) / 256, 256, 0, s>>>(d.chunk_up, d.n_chunks);
 }
 
-__global__ void k_sys_init(Dev d) {
+// advance (mxe_advance): systems keep their relaxation state, counters and
+// step budget across calls; a system given a new budget (steps_new >= 0)
+// starts afresh: counters cleared, a new relaxation, the budget set.
+__global__ void k_sys_init(Dev d, Model m, int advance) {
     const int s = gtid();
     if (s >= d.n_sys) return;
     SysCtl& c = d.ctl[s];
+    const SysDesc& S = d.sys[s];
     // A forced system rebuilds everything; otherwise its lists, pair count and
     // any pending rebuild request carry over from the previous call.
-    if (d.sys[s].force_build) {
+    if (S.force_build) {
         c.rebuild = 2;
         c.n_pairs = 0;
         c.drift_bits = 0ull;
         c.widen_bits = 0ull;
     }
     if (c.rebuild) d.acell[0].y = 1;  // the neighbour search runs
+    if (advance && S.steps_new < 0) return;
     c.status = 0;
     c.n_rebuilds = 0;
     c.total_evals = 0;
     c.pair_evals = 0.0;
     c.done = 0;
     c.k = 0;
+    c.stepping = 0;
+    if (!advance) c.steps_left = 0;  // a call of the lockstep scheme ends any step budget
+    if (advance) {
+        relax_start(c, m);
+        c.steps_left = S.n_sites > 0 ? S.steps_new : 0;
+        c.done = c.steps_left > 0 ? 0 : 1;
+        d.scalars[(int64_t)s * MXE_NSCALARS + MXE_S_STEPS_LEFT] = (double)c.steps_left;
+    }
 }
 
 // widths, occupancies, positions and site temperatures are checked
@@ -123,8 +136,8 @@ __global__ __launch_bounds__(kChunk) void k_site_init(Dev d, Model m) {
     if (st) atomicOr(&d.ctl[ch.sys].status, st);
 }
 
-void launch_sys_init(const Dev& d, const Model& m, hipStream_t s) {
-    k_sys_init<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d);
+void launch_sys_init(const Dev& d, const Model& m, hipStream_t s, int advance) {
+    k_sys_init<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d, m, advance);
     k_site_init<<<d.n_chunks, kChunk, 0, s>>>(d, m);
 }
 

@@ -47,15 +47,7 @@ __device__ inline double* sc(const Dev& d, int s) { return d.scalars + (int64_t)
 __global__ void k_relax_init(Dev d, Model m) {
     const int s = gtid();
     if (s >= d.n_sys) return;
-    SysCtl& c = d.ctl[s];
-    c.fire_dt = m.dt0;
-    c.fire_alpha = m.alpha0;
-    c.npos = 0;
-    c.k = 0;
-    c.done = 0;
-    c.converged = 0;
-    c.updates = 0;
-    c.evals = 0;
+    relax_start(d.ctl[s], m);
 }
 
 void launch_relax_init(const Dev& d, const Model& m, hipStream_t s) {
@@ -63,7 +55,9 @@ void launch_relax_init(const Dev& d, const Model& m, hipStream_t s) {
 }
 
 // One block per system: reduce the chunk partials in chunk order, then run
-// the FIRE decision (mode 1) or only record the evaluation (mode 0).
+// the FIRE decision (mode 1) or only record the evaluation (mode 0). Mode 2
+// (free-running steps) is mode 1 where a system whose relaxation ends with
+// steps left is marked to take its Euler step in this iteration.
 __global__ __launch_bounds__(kChunk) void k_control(Dev d, Model m, int mode) {
     __shared__ double lds[kChunk / kWave];
     const int s = blockIdx.x;
@@ -107,7 +101,7 @@ __global__ __launch_bounds__(kChunk) void k_control(Dev d, Model m, int mode) {
     out[MXE_S_SUMX] = sx;
     out[MXE_S_TOTAL_EVALS] = (double)c.total_evals;
     if (!isfinite(e) || !isfinite(ff)) c.status |= MXE_STAT_NONFINITE;
-    if (mode == 1) {
+    if (mode >= 1) {
         if (fm <= m.ftol) {
             c.done = 1;
             c.converged = 1;
@@ -145,6 +139,7 @@ __global__ __launch_bounds__(kChunk) void k_control(Dev d, Model m, int mode) {
             c.updates += 1;
         }
         c.k += 1;
+        if (mode == 2 && c.done && c.steps_left > 0) c.stepping = 1;
         out[MXE_S_UPDATES] = (double)c.updates;
         out[MXE_S_CONVERGED] = (double)c.converged;
         out[MXE_S_EVALS] = (double)c.evals;
@@ -156,13 +151,14 @@ void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s) {
     k_control<<<d.n_sys, kChunk, 0, s>>>(d, m, mode);
 }
 
-// Number of systems still relaxing (not done), written by one block to *out
-// (a host-mapped int): the host reads it between chunks of iterations to end a
-// relaxation once every system has finished.
-__global__ __launch_bounds__(kChunk) void k_active(const SysCtl* ctl, int n_sys, int* out) {
+// Number of systems still relaxing (not done; steps = 0) or with diffusion
+// steps left (steps = 1), written by one block to *out (a host-mapped int): the
+// host reads it between chunks of iterations to stop once it is zero.
+__global__ __launch_bounds__(kChunk) void k_active(const SysCtl* ctl, int n_sys, int steps, int* out) {
     __shared__ int lds[kChunk / kWave];
     int n = 0;
-    for (int s = threadIdx.x; s < n_sys; s += blockDim.x) n += ctl[s].done ? 0 : 1;
+    for (int s = threadIdx.x; s < n_sys; s += blockDim.x)
+        n += (steps ? ctl[s].steps_left > 0 : !ctl[s].done) ? 1 : 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = n;
@@ -174,8 +170,8 @@ __global__ __launch_bounds__(kChunk) void k_active(const SysCtl* ctl, int n_sys,
     }
 }
 
-void launch_active(const Dev& d, int* out, hipStream_t s) {
-    k_active<<<1, kChunk, 0, s>>>(d.ctl, d.n_sys, out);
+void launch_active(const Dev& d, int* out, int steps, hipStream_t s) {
+    k_active<<<1, kChunk, 0, s>>>(d.ctl, d.n_sys, steps, out);
 }
 
 // FIRE velocity mixing and position/width update; records the largest
@@ -229,9 +225,12 @@ void launch_update(const Dev& d, const Model& m, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Master equation
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kChunk) void k_flux(Dev d, Model m) {
+// free_run (mxe_advance): only systems whose relaxation ended in this
+// iteration take the step; the others' blocks leave at once (uniformly).
+__global__ __launch_bounds__(kChunk) void k_flux(Dev d, Model m, int free_run) {
     __shared__ double lds[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
+    if (free_run && !d.ctl[ch.sys].stepping) return;
     const SysDesc& S = d.sys[ch.sys];
     const int i = ch.start + threadIdx.x;
     double rate = 0.0;
@@ -286,9 +285,10 @@ __global__ __launch_bounds__(kChunk) void k_flux(Dev d, Model m) {
     if (threadIdx.x == 0) d.part[(int64_t)blockIdx.x * kNPart + P_RATE] = mx;
 }
 
-__global__ __launch_bounds__(kChunk) void k_mstep_ctl(Dev d, Model m, double dt_in) {
+__global__ __launch_bounds__(kChunk) void k_mstep_ctl(Dev d, Model m, double dt_in, int free_run) {
     __shared__ double lds[kChunk / kWave];
     const int s = blockIdx.x;
+    if (free_run && !d.ctl[s].stepping) return;
     const SysDesc& S = d.sys[s];
     // an empty slot's chunks lie beyond the launched prefix: no rows, rate 0
     const int nck = S.n_sites > 0 ? S.n_chunks : 0;
@@ -306,9 +306,10 @@ __global__ __launch_bounds__(kChunk) void k_mstep_ctl(Dev d, Model m, double dt_
 
 // Forward-Euler update of x (Sec. 4), then held-x sites are reset to their
 // value; the matter they took up in the step goes to the reservoir account.
-__global__ __launch_bounds__(kChunk) void k_euler(Dev d, Model m) {
+__global__ __launch_bounds__(kChunk) void k_euler(Dev d, Model m, int free_run) {
     __shared__ double lds[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
+    if (free_run && !d.ctl[ch.sys].stepping) return;
     const int i = ch.start + threadIdx.x;
     double xi = 0.0, taken = 0.0;
     if (i < ch.end) {
@@ -333,9 +334,12 @@ __global__ __launch_bounds__(kChunk) void k_euler(Dev d, Model m) {
     }
 }
 
-__global__ __launch_bounds__(kChunk) void k_estep_ctl(Dev d) {
+// free_run: the step is counted off the system's budget and, if steps are
+// left, its next relaxation starts with the next iteration.
+__global__ __launch_bounds__(kChunk) void k_estep_ctl(Dev d, Model m, int free_run) {
     __shared__ double lds[kChunk / kWave];
     const int s = blockIdx.x;
+    if (free_run && !d.ctl[s].stepping) return;
     const SysDesc& S = d.sys[s];
     const int nck = S.n_sites > 0 ? S.n_chunks : 0;  // as in k_mstep_ctl
     double t = 0.0, r = 0.0;
@@ -349,14 +353,21 @@ __global__ __launch_bounds__(kChunk) void k_estep_ctl(Dev d) {
     double* out = sc(d, s);
     out[MXE_S_SUMX] = t;
     out[MXE_S_RESERVOIR] += r;
-    out[MXE_S_STATUS] = (double)d.ctl[s].status;
+    SysCtl& c = d.ctl[s];
+    out[MXE_S_STATUS] = (double)c.status;
+    if (free_run) {
+        c.stepping = 0;
+        c.steps_left -= 1;
+        out[MXE_S_STEPS_LEFT] = (double)c.steps_left;
+        if (c.steps_left > 0) relax_start(c, m);
+    }
 }
 
-void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s) {
-    k_flux<<<d.n_chunks, kChunk, 0, s>>>(d, m);
-    k_mstep_ctl<<<d.n_sys, kChunk, 0, s>>>(d, m, dt_in);
-    k_euler<<<d.n_chunks, kChunk, 0, s>>>(d, m);
-    k_estep_ctl<<<d.n_sys, kChunk, 0, s>>>(d);
+void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s, int free_run) {
+    k_flux<<<d.n_chunks, kChunk, 0, s>>>(d, m, free_run);
+    k_mstep_ctl<<<d.n_sys, kChunk, 0, s>>>(d, m, dt_in, free_run);
+    k_euler<<<d.n_chunks, kChunk, 0, s>>>(d, m, free_run);
+    k_estep_ctl<<<d.n_sys, kChunk, 0, s>>>(d, m, free_run);
 }
 
 }  // namespace mxe

@@ -20,7 +20,7 @@ QUAD_GH27, QUAD_DEGREE3 = 0, 1
 RES_NONE, RES_FIX_X, RES_FIX_MU = 0, 1, 2
 NSCALARS = 16
 S_F, S_FMAX, S_DT, S_TIME, S_SUMX, S_UPDATES, S_CONVERGED, S_EVALS, S_STATUS, S_REBUILDS, \
-    S_TOTAL_EVALS, S_PAIRS, S_PAIR_EVALS, S_RESERVOIR = range(14)
+    S_TOTAL_EVALS, S_PAIRS, S_PAIR_EVALS, S_RESERVOIR, S_STEPS_LEFT = range(15)
 K_PAIR, K_DENSITY, K_FORCE, K_BUILD, K_FIRE, K_MASTER = range(6)
 KERNEL_FAMILIES = ["pair", "density", "force", "build", "fire", "master"]
 PROFILE_OFF, PROFILE_ALL, PROFILE_PAIR = 0, 1, 2  # mxe_profile modes
@@ -32,8 +32,9 @@ FATAL_STATUS = STAT_NONFINITE | STAT_X_RANGE | STAT_RHO | STAT_KMAX | STAT_PAIRS
 
 EXPORTED = ["mxe_default_params", "mxe_plan_create", "mxe_plan_destroy", "mxe_workspace_bytes",
             "mxe_plan_sites", "mxe_plan_set_system", "mxe_plan_check_system", "mxe_plan_slot_offset",
-            "mxe_plan_set_resume", "mxe_plan_layout",
-            "mxe_evaluate", "mxe_relax", "mxe_step", "mxe_run", "mxe_run_noalloc", "mxe_profile", "mxe_profile_read",
+            "mxe_plan_set_resume", "mxe_plan_layout", "mxe_plan_set_steps",
+            "mxe_evaluate", "mxe_relax", "mxe_step", "mxe_run", "mxe_advance", "mxe_run_noalloc",
+            "mxe_profile", "mxe_profile_read",
             "mxe_status_string", "mxe_last_error"]
 
 
@@ -113,6 +114,11 @@ def lib():
         L.mxe_run.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Out), C.c_int, C.c_int,
                               C.c_void_p, C.c_size_t, C.c_void_p]
         L.mxe_run.restype = C.c_int
+        L.mxe_advance.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Out), C.c_int, C.c_int,
+                                  C.c_void_p, C.c_size_t, C.c_void_p]
+        L.mxe_advance.restype = C.c_int
+        L.mxe_plan_set_steps.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.mxe_plan_set_steps.restype = C.c_int
         L.mxe_run_noalloc.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Out), C.c_int,
                                       C.c_void_p]
         L.mxe_run_noalloc.restype = C.c_int
@@ -302,6 +308,10 @@ class Plan:
     def set_resume(self, on: bool):
         _check(lib().mxe_plan_set_resume(self._h, int(bool(on))))
 
+    def set_steps(self, slot: int, n_steps: int):
+        """Budget of free-running diffusion steps for a slot, from the next advance()."""
+        _check(lib().mxe_plan_set_steps(self._h, int(slot), int(n_steps)))
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
@@ -351,6 +361,14 @@ class Plan:
         a, o = st.abi(), out.abi()
         _check(lib().mxe_run(self._h, C.byref(a), C.byref(o), int(n_steps), int(bool(use_graph)),
                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+
+    def advance(self, st: DeviceState, out: DeviceOut, ws, max_iters: int, use_graph: bool = True,
+                stream=None):
+        """Up to max_iters free-running iterations (mxe_advance); stops early once no
+        slot has steps left."""
+        a, o = st.abi(), out.abi()
+        _check(lib().mxe_advance(self._h, C.byref(a), C.byref(o), int(max_iters), int(bool(use_graph)),
+                                 C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
 
     def run_noalloc(self, st: DeviceState, out: DeviceOut, n_steps: int, stream=None):
         """mxe_run on the library's per-device scratch (no workspace argument)."""

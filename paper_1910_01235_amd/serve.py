@@ -1,13 +1,16 @@
 """Continuous batching of many independent systems on one GPU.
 
 Requests (a system, a number of diffusion steps, an arrival time) are served
-from a pool of plan slots sized to an HBM budget. At every step boundary the
-server admits the requests that have arrived into free slots (the smallest
-free slot that holds the system), then advances every resident system by one
-diffusion step of the staggered scheme with one replay of the recorded graph,
-and retires the systems that have finished. Requests that arrive while others
-run join as slots free up; their work shares every launch with the resident
-systems. A system's results do not depend on its slot or its batch-mates.
+from a pool of plan slots sized to an HBM budget. Between calls the server
+admits the requests that have arrived into free slots (the smallest free slot
+that holds the system) and retires the systems that have finished. A call
+either advances every resident system by one diffusion step of the staggered
+scheme (step level), or runs a few free-running iterations in which each
+system takes its Euler step as soon as its own relaxation ends (iteration
+level), so no system waits for a slower one at step boundaries. Requests
+that arrive while others run join as slots free up; their work shares every
+launch with the resident systems. A system's results do not depend on its
+slot, its batch-mates or the level.
 
 The one-at-a-time path serves the same stream with a single-slot plan per
 request, in arrival order, for comparison on the same GPU.
@@ -102,9 +105,18 @@ class Server:
     """A pool of slots on one GPU, with continuous batching over diffusion steps."""
 
     def __init__(self, eam: dict, params: dict, capacities: list, precision: str = "fp64",
-                 device: str = "cuda"):
+                 device: str = "cuda", iteration_level: bool = False, advance_iters: int = 8):
+        """iteration_level: systems advance with free-running steps (mxe_advance),
+        each taking its Euler step as soon as its own relaxation ends; requests
+        are admitted and retired between calls of advance_iters iterations.
+        Otherwise every resident system takes one diffusion step per call, the
+        call lasting as long as the slowest relaxation. Needs relax_chunk > 0."""
         import torch
         self.torch = torch
+        self.iteration_level = iteration_level
+        self.advance_iters = advance_iters
+        if iteration_level and int(params.get("relax_chunk", 0)) <= 0:
+            raise ValueError("iteration-level serving needs params['relax_chunk'] > 0")
         self.capacities = list(capacities)
         r_cap = eam["r_c"] + 3 * math.sqrt(2) * params.get("sigma_cap", 0.3) + params.get("skin", 0.15)
         templates = [_template(c, 2 * r_cap + 1.0) for c in self.capacities]
@@ -144,11 +156,13 @@ class Server:
                 return k
             free.discard(k)
 
-    def admit(self, slot: int, s: L.System):
+    def admit(self, slot: int, s: L.System, n_steps: int = 0):
         torch = self.torch
         off = int(self.plan.offsets[slot])
         n = s.n
         self.plan.set_system(slot, s)
+        if self.iteration_level:
+            self.plan.set_steps(slot, n_steps)
         f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=self.device)
         self.st.qx[off:off + n] = f(s.q[:, 0])
         self.st.qy[off:off + n] = f(s.q[:, 1])
@@ -171,7 +185,12 @@ class Server:
         self.free.add(slot)
 
     def step(self):
-        self.plan.run(self.st, self.out, self.ws, 1, use_graph=True)
+        """One call: a diffusion step of every resident system, or (iteration
+        level) up to advance_iters free-running iterations."""
+        if self.iteration_level:
+            self.plan.advance(self.st, self.out, self.ws, self.advance_iters, use_graph=True)
+        else:
+            self.plan.run(self.st, self.out, self.ws, 1, use_graph=True)
 
     def serve(self, requests: list, realtime: bool = True, progress=None):
         """Serve a request stream; returns (results, rejected ids, stats).
@@ -200,7 +219,7 @@ class Server:
                 if slot is None:
                     keep.append(r)
                     continue
-                self.admit(slot, r.system)
+                self.admit(slot, r.system, r.n_steps)
                 active[slot] = [r, 0, now()]
             pending = keep
             if not active:
@@ -213,10 +232,14 @@ class Server:
             busy += now() - ts
             steps += 1
             done = []
-            for slot, rec in active.items():
-                rec[1] += 1
-                if rec[1] >= rec[0].n_steps:
-                    done.append(slot)
+            if self.iteration_level:
+                left = self.out.scalars.view(-1, mxe.NSCALARS)[:, mxe.S_STEPS_LEFT].cpu().numpy()
+                done = [slot for slot in active if left[slot] == 0]
+            else:
+                for slot, rec in active.items():
+                    rec[1] += 1
+                    if rec[1] >= rec[0].n_steps:
+                        done.append(slot)
             tc = now()
             for slot in done:
                 r, _, ta = active.pop(slot)

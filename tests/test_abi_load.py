@@ -65,6 +65,21 @@ def test_plan_validation_needs_no_gpu():
         with pytest.raises(mxe.MxeError, match="relax_chunk"):
             mxe.Plan(w.systems, w.eam, dict(w.params, relax_chunk=bad))
     assert mxe.Plan(w.systems, w.eam, dict(w.params, relax_chunk=4)).params.relax_chunk == 4
+    # free-running steps: argument checks precede any device work
+    L_ = mxe.lib()
+    p0 = mxe.Plan(w.systems, w.eam, w.params)
+    assert L_.mxe_advance(p0._h, None, None, 10, 1, None, 0, None) == -1  # relax_chunk 0
+    assert b"relax_chunk" in L_.mxe_last_error()
+    p4 = mxe.Plan(w.systems, w.eam, dict(w.params, relax_chunk=4))
+    assert L_.mxe_advance(p4._h, None, None, 10, 1, None, 0, None) == -1  # resume mode off
+    assert b"resume" in L_.mxe_last_error()
+    p4.set_resume(True)
+    assert L_.mxe_advance(p4._h, None, None, -1, 1, None, 0, None) == -1
+    with pytest.raises(mxe.MxeError, match="slot"):
+        p4.set_steps(5, 3)
+    with pytest.raises(mxe.MxeError, match="n_steps"):
+        p4.set_steps(0, -1)
+    p4.set_steps(0, 3)
     # fp32 workspace is smaller (FP32 moments)
     p32 = mxe.Plan(w.systems, w.eam, w.params, precision="fp32")
     assert p32.ws_bytes < plan.ws_bytes
