@@ -253,12 +253,20 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
     shapes_pool = {k: tuned_pool[k] for k in autotune.SHAPES}
     log(f"serving: pool shapes {shapes_pool}")
 
-    def batched(p):
+    def batched(p, free=False):
+        """All requests in one plan: lockstep steps (mxe_run) or free-running
+        steps (mxe_advance, each system stepping as soon as it has relaxed)."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plan = mxe.Plan(systems, L.DEFAULT_EAM, p)
         st, out, ws = plan.state(systems), plan.out(), plan.workspace()
-        plan.run(st, out, ws, n_steps, use_graph=True)
+        if free:
+            plan.set_resume(True)
+            for k in range(len(systems)):
+                plan.set_steps(k, n_steps)
+            plan.advance(st, out, ws, 1 << 30, use_graph=True)
+        else:
+            plan.run(st, out, ws, n_steps, use_graph=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         sc = plan.scalars(out)
@@ -320,9 +328,11 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
 
     # early exit (the product's schedule)
     p_b = dict(params, relax_chunk=RELAX_CHUNK_BATCHED)
-    bat, x_b = batched(p_b)
+    bat, x_b = batched(p_b, free=True)
     cap = bat["systems_per_s"]
-    log(f"serving: batched {bat['wall_s']:.1f} s, {cap:.1f} systems/s")
+    log(f"serving: batched (free-running steps) {bat['wall_s']:.1f} s, {cap:.1f} systems/s")
+    bat_l, x_l = batched(p_b)
+    log(f"serving: batched (lockstep) {bat_l['wall_s']:.1f} s")
     one, service, res1 = one_at_a_time(params, lambda s: single[id(s)], "early exit")
     p_pool = dict(params_pool, relax_chunk=RELAX_CHUNK_BATCHED)
     srv_rows, n_slots, fp = served(p_pool, [(f, f * cap) for f in rate_factors], service,
@@ -333,9 +343,10 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
     log(f"serving: batched, fixed sequence {bat0['wall_s']:.1f} s")
     one0, service0, res0 = one_at_a_time(params, None, "fixed sequence")
     srv0, _, _ = served(params, [(f, f * cap) for f in before_rates], service0, "fixed sequence")
-    # the batched runs differ only in the schedule: bitwise equal; the one-at-a-time
-    # runs also differ in launch shapes (lanes per site reorder sums): to rounding
-    same = all(np.array_equal(a, b) for a, b in zip(x_b, x_b0))
+    # the three batched runs (free-running, lockstep, fixed sequence) differ only
+    # in the schedule: bitwise equal; the one-at-a-time runs also differ in
+    # launch shapes (lanes per site reorder sums): to rounding
+    same = all(np.array_equal(a, b) and np.array_equal(a, c) for a, b, c in zip(x_b, x_b0, x_l))
     dx = max(float(np.abs(a.x - b.x).max()) for a, b in zip(sorted(res1, key=lambda r: r.rid),
                                                             sorted(res0, key=lambda r: r.rid)))
     return dict(requests=len(systems), sites=n_tot, steps_per_request=n_steps,
@@ -343,12 +354,13 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
                 shapes_server=shapes_pool,
                 relax_chunk=dict(batched=RELAX_CHUNK_BATCHED, served=RELAX_CHUNK_BATCHED,
                                  one_at_a_time=RELAX_CHUNK_SINGLE),
-                batched=bat, one_at_a_time=one, batched_vs_one_at_a_time=cap / one["systems_per_s"],
+                batched=bat, batched_lockstep=bat_l, one_at_a_time=one,
+                batched_vs_one_at_a_time=cap / one["systems_per_s"],
                 served=srv_rows, server="iteration level: free-running steps, "
                 f"calls of {ADVANCE_ITERS} iterations", served_step_level=srv_step,
                 slots=n_slots, footprint_gb=fp,
                 fixed_sequence=dict(batched=bat0, one_at_a_time=one0, served=srv0,
-                                    batched_x_bitwise_equal=bool(same),
+                                    batched_x_bitwise_equal_all_schedules=bool(same),
                                     one_at_a_time_max_abs_dx=dx))
 
 
