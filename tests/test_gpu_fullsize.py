@@ -45,7 +45,7 @@ CASES = [("c1_vacancy_256k", lambda: L.config1(1), "fp64"),
          ("c1_vacancy_256k", lambda: L.config1(1), "fp32"),
          ("c2_alloy_slab_131k", lambda: L.config2(2), "fp32"),
          ("c2_alloy_slab_131k", lambda: L.config2(2), "fp64"),
-         ("c3_nanowire_265k", lambda: L.config3(3), "fp32")]
+         ("c3_nanowire_256k", lambda: L.config3(3), "fp32")]
 
 
 @pytest.mark.parametrize("name,maker,prec", CASES, ids=[f"{c[0]}-{c[2]}" for c in CASES])

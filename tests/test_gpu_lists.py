@@ -40,7 +40,7 @@ def _cases():
     yield "c1_jittered", L.jitter(w1.systems[0], 11, dq=0.05, sig=(0.07, 0.13)), w1, 0
     yield "c1_jittered_degree3", L.jitter(w1.systems[0], 12, dq=0.05, sig=(0.07, 0.13)), w1, 1
     w3 = L.config3(3)
-    yield "c3_nanowire_265k", w3.systems[0], w3, 0
+    yield "c3_nanowire_256k", w3.systems[0], w3, 0
 
 
 @pytest.mark.parametrize("name,s,w,rule", list(_cases()), ids=lambda v: v if isinstance(v, str) else "")

@@ -5,7 +5,7 @@
   every step's update count, convergence flag, free energy, max |f|, time
   step and sum of x compared;
 * one-step prefixes of the three large workloads at their full sizes (256,000
-  vacancy sites in FP64; the 131,072-site alloy slab and the 265k-site
+  vacancy sites in FP64; the 131,072-site alloy slab and the 256k-site
   nanowire in FP32-mixed, their workloads' precision), with the relaxation cut
   to 3 updates so the oracle finishes in seconds;
 * a request of the serving sweep, served in a mix, against the oracle;
@@ -128,7 +128,7 @@ def test_plain_workload_full_run_matches_oracle(mx, use_graph):
 def _prefix_cases():
     yield "c1_vacancy_256k", L.config1(1), "fp64"
     yield "c2_alloy_slab_131k", L.config2(2), "fp32"
-    yield "c3_nanowire_265k", L.config3(3), "fp32"
+    yield "c3_nanowire_256k", L.config3(3), "fp32"
 
 
 @pytest.mark.parametrize("name,w,precision", list(_prefix_cases()), ids=lambda v: v if isinstance(v, str) else "")
