@@ -708,6 +708,22 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_single_sample, c0_oracle_s)
+    # every run's device status: a bit that marks results invalid anywhere is listed
+    bad = []
+
+    def walk(o, path):
+        if isinstance(o, dict):
+            for k, v in o.items():
+                if k == "status" and isinstance(v, int) and v & mxe.FATAL_STATUS:
+                    bad.append(f"{path}/{k}={v}")
+                walk(v, f"{path}/{k}")
+        elif isinstance(o, list):
+            for i, v in enumerate(o):
+                walk(v, f"{path}[{i}]")
+    walk(result, "")
+    result["invalid_results"] = bad
+    if bad:
+        log(f"results flagged invalid: {bad}")
     print(json.dumps(result), flush=True)
 
 
