@@ -56,10 +56,10 @@ BREAKDOWN_STEPS = 2
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="db0d119be0145a6d",
-    pair=dict(fetch_kib=70720.2, write_kib=1019787.0),
-    force=dict(fetch_kib=896904.3, write_kib=13679.7),
-    density=dict(fetch_kib=137313.7, write_kib=27103.9),
+    sources_sha256_16="512c6dc1414a5178",
+    pair=dict(fetch_kib=71056.4, write_kib=1019787.0),
+    force=dict(fetch_kib=896894.8, write_kib=13693.8),
+    density=dict(fetch_kib=137325.6, write_kib=27109.7),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -78,11 +78,11 @@ def counter_traffic(family: str):
 # VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
 # Valid only for the sources they were taken on.
 VALU_COUNTERS = dict(
-    sources_sha256_16="db0d119be0145a6d",
-    pair=dict(SQ_INSTS_VALU=226717400.6, SQ_INSTS_VALU_FMA_F64=121838355.2,
-              SQ_INSTS_VALU_MUL_F64=29613842.6, SQ_INSTS_VALU_ADD_F64=12554670.2,
-              SQ_INSTS_VALU_TRANS_F64=3222592.0, SQ_INSTS_VALU_FLOPS_FP64=289069849.9,
-              VALUBusy=71.30, VALUUtilization=90.37),
+    sources_sha256_16="512c6dc1414a5178",
+    pair=dict(SQ_INSTS_VALU=226718612.5, SQ_INSTS_VALU_FMA_F64=121839303.8,
+              SQ_INSTS_VALU_MUL_F64=29613988.7, SQ_INSTS_VALU_ADD_F64=12554662.7,
+              SQ_INSTS_VALU_TRANS_F64=3222596.6, SQ_INSTS_VALU_FLOPS_FP64=289069864.3,
+              VALUBusy=71.80, VALUUtilization=90.36),
 )
 
 
