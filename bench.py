@@ -129,36 +129,92 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(workload, n_sample: int, n_single: int, c0_oracle_s=None):
-    """The CPU oracle timed on bounded samples of the same state: one evaluation
-    of the first n_sample sites with OpenMP on every host thread, and of the first
-    n_single sites on one thread."""
+def cpu_baseline(workload, n_sample: int, n_single: int, c0_oracle_s=None, gpu=None):
+    """The CPU oracle timed on bounded samples of the same states (about 15 s of
+    CPU work on a 16-thread host). A sampled evaluation still searches the
+    neighbours of the whole system, so samples are whole systems where the
+    rate is the point:
+    * `value`: one evaluation of the first n_sample sites of the 256k-site
+      workload with OpenMP on every host thread (median of 3 repeats);
+    * `single_thread`: the first n_single sites on one thread;
+    * `per_eval`: one evaluation of every site of the slab and nanowire
+      workloads on every host thread;
+    * `master_step`: the kinetic law's rates over all 256k sites (bonds built
+      beforehand, untimed), median of 3;
+    * `extrapolated`: full-run times from these rates and the GPU runs'
+      evaluation counts (labelled as extrapolated: not run)."""
     import numpy as np
 
     import oracle as O
-    s = workload.systems[0]
+    from paper_1910_01235_amd import lattice as L
     O.lib()
     cores = O.num_threads()
 
-    def rate(n):
+    def eval_rate(w, n, repeats=3):
+        s = w.systems[0]
         sel = np.arange(min(n, s.n), dtype=np.int32)
-        t0 = time.perf_counter()
-        O.evaluate_sites(workload.eam, s.box, s.periodic, s.T, s.q, s.sigma, s.x, s.type, sel)
-        return len(sel), time.perf_counter() - t0
+        dts = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            O.evaluate_sites(w.eam, s.box, s.periodic, s.T, s.q, s.sigma, s.x, s.type, sel)
+            dts.append(time.perf_counter() - t0)
+        return len(sel), float(np.median(dts))
 
-    n_all, dt_all = rate(n_sample)
+    s = workload.systems[0]
+    n_all, dt_all = eval_rate(workload, n_sample)
     O.set_num_threads(1)
     try:
-        n_one, dt_one = rate(n_single)
+        n_one, dt_one = eval_rate(workload, n_single, repeats=1)
     finally:
         O.set_num_threads(cores)
     out = dict(value=n_all / dt_all, unit="site-evals/s", cores=cores, kind="oracle",
                sample=f"one evaluation (density pass over the sample and its neighbours, force/mu "
                       f"pass over the sample) of the first {n_all} of {s.n} sites of the "
-                      f"initial state; {dt_all:.2f} s wall on {cores} threads",
+                      f"initial state; median {dt_all:.2f} s wall of 3 repeats on {cores} threads",
                cpu_model=cpu_model(), nproc=os.cpu_count(),
                single_thread=dict(value=n_one / dt_one, unit="site-evals/s", cores=1,
                                   sample=f"first {n_one} sites, {dt_one:.2f} s wall"))
+    per_eval = {workload.name: dict(value=n_all / dt_all, unit="site-evals/s", sites=n_all)}
+    for w2 in (L.config2(2), L.config3(3)):
+        n2, dt2 = eval_rate(w2, w2.systems[0].n, repeats=1)
+        per_eval[w2.name] = dict(value=n2 / dt2, unit="site-evals/s", sites=n2)
+    out["per_eval"] = per_eval
+    # the kinetic law over every site of the 256k-site state (mu = 0: the same work)
+    p = workload.params
+    nb, bl = O.bonds(s.box, s.periodic, s.q, s.type, p["r_bond"])
+    mu = np.zeros(s.n)
+    dts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        O.master_rates(p, s.box, s.periodic, s.T, s.x, s.type, mu, nb, bl)
+        dts.append(time.perf_counter() - t0)
+    n_mob = int((s.type != L.HOST_FIXED).sum())
+    out["master_step"] = dict(value=n_mob / float(np.median(dts)), unit="site-steps/s",
+                              sample=f"rates and time step of all {n_mob} mobile sites, median of 3")
+    # full runs, extrapolated: evaluations per step as the GPU runs measured them
+    ext = {}
+    gpu = gpu or {}
+    for name, n_sites, n_steps, leg in ((workload.name, s.n, workload.n_steps, gpu),
+                                        ("c2_alloy_slab_131k", 131072, 500, gpu.get("c2_alloy_slab_131k")),
+                                        ("c3_nanowire_256k", 256410, 300, gpu.get("c3_nanowire_256k"))):
+        if not leg or name not in per_eval:
+            continue
+        ev = leg.get("evals", leg.get("evals_in_timed_steps"))
+        ev_per_step = ev / leg["steps"] if ev and leg.get("steps") else None
+        if ev_per_step is None:
+            continue
+        t = n_steps * ev_per_step * n_sites / per_eval[name]["value"]
+        ext[name] = dict(seconds=t, steps=n_steps, evals_per_step=ev_per_step,
+                         note="extrapolated: steps x evaluations per step (GPU run) x sites / "
+                              "the oracle's all-thread rate; not run")
+    srv = gpu.get("serving")
+    if srv:
+        site_evals = srv["batched"]["site_evals_per_s"] * srv["batched"]["wall_s"]
+        ext["serving_256_requests"] = dict(
+            seconds=site_evals / per_eval[workload.name]["value"],
+            note="extrapolated: the batched run's site-evaluations / the oracle's all-thread rate "
+                 "on the 256k-site state; not run")
+    out["extrapolated"] = ext
     if c0_oracle_s is not None:
         out["c0_full_run_s"] = c0_oracle_s
         out["c0_full_run_cores"] = cores
@@ -707,7 +763,8 @@ def main():
         result["calib_copy_bytes"] = a.numel() * 8
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_single_sample, c0_oracle_s)
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_single_sample, c0_oracle_s,
+                                              gpu=result)
     # every run's device status: a bit that marks results invalid anywhere is listed
     bad = []
 
