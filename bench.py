@@ -495,6 +495,34 @@ def fullsize_leg(w, precision, steps, warmup, quad_rule=0, params=None, late=0):
     return res
 
 
+def full_run_leg(w, precision, params=None):
+    """A workload's whole configured run (all its diffusion steps) as one call
+    of graph replays: the end-to-end wall time, with the state uploaded first
+    (not timed)."""
+    import torch
+
+    from paper_1910_01235_amd import mxe
+    s = w.systems[0]
+    if params is None:
+        params, shapes = tuned(w, precision)
+    else:
+        from paper_1910_01235_amd import autotune
+        shapes = {k: params.get(k) for k in autotune.SHAPES}
+    plan = mxe.Plan([s], w.eam, params, precision=precision)
+    st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+    wall, sc, _ = timed_run(plan, st, out, ws, w.n_steps, use_graph=True, profile=False)
+    ev = int(sc[mxe.S_TOTAL_EVALS])
+    n_mobile = int((s.type != 3).sum())
+    res = dict(workload=w.name, sites=s.n, precision=precision, steps=w.n_steps, launch_shapes=shapes,
+               wall_s=wall, evals=ev, value=s.n * ev / wall, unit="site-evals/s",
+               site_steps_per_s=n_mobile * w.n_steps / wall, list_builds=int(sc[mxe.S_REBUILDS]),
+               simulated_time_s=float(sc[mxe.S_TIME]), status=int(sc[mxe.S_STATUS]),
+               launch="one call, graph replays")
+    del st, out, ws, plan
+    torch.cuda.empty_cache()
+    return res
+
+
 def c0_leg():
     """The plain-method workload end to end: 256 sites, 20 diffusion steps of up
     to 50 FIRE updates, graph replays, against the oracle's run. Relaxations end
@@ -557,7 +585,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline leg (no other legs, no oracle errors)")
-    ap.add_argument("--legs", default="graph,fp32,degree3,variants,c0,c2,c3,serving",
+    ap.add_argument("--legs", default="graph,fp32,degree3,variants,c0,c2,c3,full,serving",
                     help="comma-separated extra legs")
     ap.add_argument("--fullsize-steps", type=int, default=3,
                     help="timed diffusion steps of the slab and nanowire legs")
@@ -681,6 +709,10 @@ def main():
         "pair_ms_avg_timed": pair_ms / max(pair_launches, 1),
         "kernel_ms": fam,
         "kernel_ms_from": f"{BREAKDOWN_STEPS} steps after the timed region, every family bracketed",
+        # kernel-only rate: the sites over the summed kernel time per evaluation
+        # (every family's event time of the breakdown steps / their evaluations)
+        "kernel_only_site_evals_per_s": n * evals_b / max(sum(v["ms_total"] for v in fam.values()) / 1e3,
+                                                         1e-30),
         "dominant_kernel": dominant,
     }
     if legs:
@@ -747,6 +779,15 @@ def main():
     if "c3" in legs:
         result["c3_nanowire_256k"] = fullsize_leg(L.config3(3), "fp32", args.fullsize_steps, 1, late=10)
         log(f"nanowire leg: {result['c3_nanowire_256k']['value']:.4g} site-evals/s")
+    if "full" in legs:
+        # whole configured runs, end to end (the 256k-site workload in FP64, the
+        # slab and the nanowire in their FP32-mixed precision)
+        result["full_runs"] = {}
+        for wf, prec, pf in ((w, "fp64", params), (L.config2(2), "fp32", None), (L.config3(3), "fp32", None)):
+            r = full_run_leg(wf, prec, pf)
+            result["full_runs"][wf.name] = r
+            log(f"full run {wf.name}: {r['steps']} steps in {r['wall_s']:.2f} s, "
+                f"{r['value']:.4g} site-evals/s, status {r['status']}")
     if "serving" in legs:
         t0 = time.perf_counter()
         rates = [float(x) for x in args.serve_rates.split(",") if x]

@@ -138,14 +138,23 @@ def config1(seed: int = 1) -> Workload:
     return Workload("c1_vacancy_256k", [s], params=p, n_steps=100)
 
 
+# FCC spacing at which the analytic EAM's energy per atom of species A is lowest
+# at T = 0 (3.813 A for pair 0.3 exp(-8 (r/2.556 - 1)), density
+# exp(-6 (r/2.556 - 1)), F = -sqrt(rho), cosine taper 4.5-5.0 A): a free surface
+# needs the crystal near its own spacing
+A0_EAM = 3.81
+
+
 def config2(seed: int = 2) -> Workload:
-    """Binary alloy slab: 32^3 cells (131,072 sites), periodic x,y, 20 A vacuum in z, T = 900 K."""
+    """Binary alloy slab: 32^3 cells (131,072 sites), periodic x,y, 20 A vacuum in z
+    (10 A on each side), T = 900 K, at the potential's own FCC spacing A0_EAM."""
     n_c = 32
-    q = fcc(n_c, n_c, n_c)
+    q = fcc(n_c, n_c, n_c, A0_EAM)
+    q[:, 2] += 10.0
     n = q.shape[0]
     rng = np.random.default_rng(seed)
     x = 0.05 + rng.uniform(-0.01, 0.01, n)
-    L = n_c * A0_CU
+    L = n_c * A0_EAM
     s = System(q, np.full(n, 0.1), x, np.full(n, ALLOY, np.int8), (L, L, L + 20.0),
                (True, True, False), 900.0, "c2_alloy_slab_131k")
     p = dict(DEFAULT_PARAMS, max_relax=30)
