@@ -194,9 +194,11 @@ def cpu_baseline(workload, n_sample: int, n_single: int, c0_oracle_s=None, gpu=N
     # full runs, extrapolated: evaluations per step as the GPU runs measured them
     ext = {}
     gpu = gpu or {}
+    full = gpu.get("full_runs", {})
     for name, n_sites, n_steps, leg in ((workload.name, s.n, workload.n_steps, gpu),
                                         ("c2_alloy_slab_131k", 131072, 500, gpu.get("c2_alloy_slab_131k")),
                                         ("c3_nanowire_256k", 256410, 300, gpu.get("c3_nanowire_256k"))):
+        leg = full.get(name, leg)  # the whole run's evaluation count where it was run
         if not leg or name not in per_eval:
             continue
         ev = leg.get("evals", leg.get("evals_in_timed_steps"))
@@ -205,8 +207,8 @@ def cpu_baseline(workload, n_sample: int, n_single: int, c0_oracle_s=None, gpu=N
             continue
         t = n_steps * ev_per_step * n_sites / per_eval[name]["value"]
         ext[name] = dict(seconds=t, steps=n_steps, evals_per_step=ev_per_step,
-                         note="extrapolated: steps x evaluations per step (GPU run) x sites / "
-                              "the oracle's all-thread rate; not run")
+                         note="extrapolated: steps x evaluations per step (GPU run, the whole run "
+                              "where it was timed) x sites / the oracle's all-thread rate; not run")
     srv = gpu.get("serving")
     if srv:
         site_evals = srv["batched"]["site_evals_per_s"] * srv["batched"]["wall_s"]
@@ -718,6 +720,9 @@ def main():
             steps=BREAKDOWN_STEPS, evals=evals_b,
             note="breakdown steps after the timed region, every kernel family bracketed by events"),
         "dominant_kernel": dominant,
+        # the Euler step of the kinetic law on its own (event time per step)
+        "master_step_site_steps_per_s": (int((s.type != 3).sum()) / (fam["master"]["ms_avg"] / 1e3)
+                                         if fam["master"]["ms_avg"] > 0 else None),
     }
     if legs:
         result["error_vs_oracle"] = sampled_errors(w, plan, st, out, ws, "fp64")
