@@ -338,6 +338,16 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     m.pair_block = p.pair_block ? p.pair_block : 256;
     m.pair_shift = 0;
     while ((1 << m.pair_shift) < (p.pair_split ? p.pair_split : 2)) ++m.pair_shift;
+    // exponent ratios alpha : gamma = P : Q per pair class, in lowest terms
+    for (int c = 0; c < 2; ++c) {
+        m.ratio_pq[c] = 0;
+        const double al = eam->alpha[c], ga = eam->gamma[c];
+        for (int q = 1; q <= 15 && !m.ratio_pq[c]; ++q)
+            for (int pp = 1; pp <= 15 && !m.ratio_pq[c]; ++pp)
+                if (std::fabs(al * q - ga * pp) <= 1e-12 * std::fmax(std::fabs(al), std::fabs(ga)) && al > 0 &&
+                    ga > 0)
+                    m.ratio_pq[c] = pp * 16 + q;
+    }
     m.quad_rule = p.quad_rule;
     // near-minimax remainder polynomials of node_poly.h
     static_assert(sizeof(kExpE) == sizeof(m.poly.ex) && sizeof(kTaperS) == sizeof(m.poly.sn) &&

@@ -99,12 +99,35 @@ __device__ inline void taper_terms(double z, double& S, double& sn, const PolyCo
 template <typename T>
 struct ShapeK {
     T p1, p0, f1, f0;  // base-2 exponents: -a (r/r_e - 1) log2(e) = r x1 + x0
+    T u1, u0;          // the same for u = exp(-(alpha / P) t) (ratio kernels only)
+    bool second;       // the pair is of the second ratio of a two-ratio kernel
     T kp, kf;          // a / r_e: minus the slope of each natural exponent
     T r_s, tw;         // taper start and 1 / taper width
     T kz, kd;          // pi / width (the taper's z per unit distance), -pi / (2 width)
 };
 
-template <typename T>
+// Exponent ratios. When alpha : gamma = P : Q in small integers, both radial
+// exponentials are powers of one: exp(-alpha t) = u^P and exp(-gamma t) = u^Q
+// with u = exp(-(alpha / P) t), t = r / r_e - 1. A ratio code kPQ = 16 P + Q
+// (0: two exponentials) is a compile-time property of the pair kernel; the
+// host picks the kernel whose codes match the potential's classes.
+template <int kPQ> constexpr int kRatioP = kPQ >> 4;
+template <int kPQ> constexpr int kRatioQ = kPQ & 15;
+
+// u^n by squaring, with the squares shared between the two powers
+template <int n, typename T>
+__device__ inline T ipow(T u) {
+    static_assert(n >= 1 && n <= 15, "power");
+    if constexpr (n == 1) return u;
+    else if constexpr (n % 2 == 0) {
+        const T h = ipow<n / 2>(u);
+        return h * h;
+    } else {
+        return ipow<n - 1>(u) * u;
+    }
+}
+
+template <typename T, int kPQ = 0, int kPQ1 = kPQ>
 __device__ inline ShapeK<T> shape_consts(const Model& m, int cls) {
     constexpr double kLog2e = 1.4426950408889634;
     constexpr double kPi = 3.141592653589793;
@@ -114,6 +137,13 @@ __device__ inline ShapeK<T> shape_consts(const Model& m, int cls) {
     k.p0 = (T)(al * kLog2e);
     k.f1 = (T)(-ga * ir * kLog2e);
     k.f0 = (T)(ga * kLog2e);
+    k.u1 = k.u0 = T(0);
+    k.second = kPQ1 != kPQ && cls != 0;
+    if constexpr (kPQ != 0) {
+        const double g = al / (k.second ? kRatioP<kPQ1> : kRatioP<kPQ>);
+        k.u1 = (T)(-g * ir * kLog2e);
+        k.u0 = (T)(g * kLog2e);
+    }
     k.kp = (T)(al * ir);
     k.kf = (T)(ga * ir);
     k.r_s = (T)m.r_s;
@@ -145,16 +175,36 @@ template <> struct Math<float> {
     }
 };
 
-// Both radial shapes and their derivatives at distance r (r < r_c).
-template <typename T>
+// Both radial shapes and their derivatives at distance r (r < r_c). A
+// two-ratio kernel (kPQ1 != kPQ) serves pairs of ratio P+1 : Q+1 with the same
+// body: one more factor u on both powers, chosen per lane and folded into the
+// taper value, so that it costs no multiply below the taper's start.
+template <typename T, int kPQ = 0, int kPQ1 = kPQ>
 __device__ inline void shapes(T r, const ShapeK<T>& k, T& gp, T& dgp, T& gf, T& dgf, const PolyCoef& pc) {
-    const T ep = Math<T>::ex2(fma(r, k.p1, k.p0), pc);
-    const T ef = Math<T>::ex2(fma(r, k.f1, k.f0), pc);
-    T S = T(1), dS = T(0);
+    T ep, ef, t = T(1);
+    if constexpr (kPQ != 0) {
+        const T u = Math<T>::ex2(fma(r, k.u1, k.u0), pc);
+        ep = ipow<kRatioP<kPQ>>(u);
+        ef = ipow<kRatioQ<kPQ>>(u);
+        if constexpr (kPQ1 != kPQ) {
+            static_assert(kRatioP<kPQ1> == kRatioP<kPQ> + 1 && kRatioQ<kPQ1> == kRatioQ<kPQ> + 1,
+                          "two-ratio kernels differ by one in both powers");
+            t = k.second ? u : T(1);
+        }
+    } else {
+        ep = Math<T>::ex2(fma(r, k.p1, k.p0), pc);
+        ef = Math<T>::ex2(fma(r, k.f1, k.f0), pc);
+    }
+    // the factor t common to both shapes rides on the taper: S t and S' t
+    T S = t, dS = T(0);
     if (r > k.r_s) {
         T sn;
         Math<T>::taper(r - k.r_s, k, S, sn, pc);
         dS = k.kd * sn;
+        if constexpr (kPQ1 != kPQ) {
+            S *= t;
+            dS *= t;
+        }
     }
     gp = ep * S;
     dgp = ep * (dS - k.kp * S);
@@ -170,11 +220,11 @@ __device__ inline void shapes(T r, const ShapeK<T>& k, T& gp, T& dgp, T& gf, T& 
 // P_k, M_k sum c_n over the nodes with zeta_k = +1 and -1. So a node only adds
 // c_n to a few sums: to its x plane a (whose three sums give A, P_x and M_x)
 // and to the y and z sums its offset selects.
-template <typename T>
+template <typename T, int kPQ = 0, int kPQ1 = kPQ>
 __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, double ry, double rz,
                                          double s, T out[kFBlk]) {
     constexpr T kSqrt3 = T(1.7320508075688772935);
-    const ShapeK<T> K = shape_consts<T>(m, cls);
+    const ShapeK<T> K = shape_consts<T, kPQ, kPQ1>(m, cls);
     const T rc2 = (T)(m.r_c * m.r_c);
     const T h = (T)s * kSqrt3;
     const T R[3] = {(T)rx, (T)ry, (T)rz};
@@ -202,7 +252,7 @@ __device__ inline void pair_moments_gh27(const Model& m, int cls, double rx, dou
                     const T rinv = Math<T>::rsq(r2);
                     const T r = r2 * rinv;
                     T gp, dgp, gf, dgf;
-                    shapes<T>(r, K, gp, dgp, gf, dgf, m.poly);
+                    shapes<T, kPQ, kPQ1>(r, K, gp, dgp, gf, dgf, m.poly);
                     const T wr = W * rinv;
                     const T cp = wr * dgp, cf = wr * dgf;
                     out[M_PHI] += W * gp;
@@ -268,12 +318,12 @@ __device__ inline void density_shape(T r, const ShapeK<T>& k, T& g, T& dg, const
 // Degree-3 rule of App. A in the pair's six coordinates. A node that moves the
 // lo end by -c h e_a or the hi end by +c h e_a (h = sqrt(6) sigma_end, c = +-1)
 // sits at d = rbar + c h e_a, and d.(dd/dsigma_end) = c sqrt(6) d_a.
-template <typename T>
+template <typename T, int kPQ = 0, int kPQ1 = kPQ>
 __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, double ry, double rz,
                                        double si, double sj, T out[kFBlk]) {
     constexpr T kSqrt6 = T(2.4494897427831780982);
     constexpr T W = T(1.0 / 12.0);
-    const ShapeK<T> K = shape_consts<T>(m, cls);
+    const ShapeK<T> K = shape_consts<T, kPQ, kPQ1>(m, cls);
     const T rc2 = (T)(m.r_c * m.r_c);
     const T R[3] = {(T)rx, (T)ry, (T)rz};
     const T R2[3] = {R[0] * R[0], R[1] * R[1], R[2] * R[2]};
@@ -301,7 +351,7 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
                     const T rinv = Math<T>::rsq(r2);
                     const T r = r2 * rinv;
                     T gp, dgp, gf, dgf;
-                    shapes<T>(r, K, gp, dgp, gf, dgf, m.poly);
+                    shapes<T, kPQ, kPQ1>(r, K, gp, dgp, gf, dgf, m.poly);
                     const T cp = W * dgp * rinv, cf = W * dgf * rinv;
                     out[M_PHI] += W * gp;
                     out[M_F] += W * gf;
@@ -361,7 +411,10 @@ struct alignas(16) Vec16 {
 
 // The 16 moments of one pair from its mean separation (before the minimum
 // image), its two widths and its class.
-template <typename T, int kRule>
+// kPQ0, kPQ1: the ratio codes the kernel is compiled for, per pair class
+// (host-host, host-interstitial), served by one body (two bodies in one
+// loop spill at the FP64 kernels' 128 VGPRs).
+template <typename T, int kRule, int kPQ0 = 0, int kPQ1 = 0>
 __device__ inline void pair_all_moments(const Model& m, const SysDesc& S, double rx, double ry,
                                         double rz, double si, double sj, int cls, T out[kFBlk]) {
 #pragma unroll
@@ -372,14 +425,14 @@ __device__ inline void pair_all_moments(const Model& m, const SysDesc& S, double
     // 3 s from rbar under the product rule, sqrt(6) max(sigma) under degree 3
     const double reach = kRule == MXE_QUAD_DEGREE3 ? 2.449489742783178 * fmax(si, sj) : 3.0 * s;
     if (cls >= 0 && rx * rx + ry * ry + rz * rz < (m.r_c + reach) * (m.r_c + reach)) {
-        if (kRule == MXE_QUAD_DEGREE3) pair_moments_d3<T>(m, cls, rx, ry, rz, si, sj, out);
-        else pair_moments_gh27<T>(m, cls, rx, ry, rz, s, out);
+        if (kRule == MXE_QUAD_DEGREE3) pair_moments_d3<T, kPQ0, kPQ1>(m, cls, rx, ry, rz, si, sj, out);
+        else pair_moments_gh27<T, kPQ0, kPQ1>(m, cls, rx, ry, rz, s, out);
     }
 }
 
 // The FP64 kernels are held at 128 VGPRs (4 waves per SIMD): the 27-node
 // kernel's node sums would otherwise take 131 and drop to 3 waves.
-template <typename T, int kBS, int kRule>
+template <typename T, int kBS, int kRule, int kPQ0 = 0, int kPQ1 = 0>
 __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1)))
 void k_pair(Dev d, Model m) {
     // Two latency measures, used where they measured faster (the FP64 kernels
@@ -422,6 +475,7 @@ void k_pair(Dev d, Model m) {
             for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
             if (cls >= 0 && rx * rx + ry * ry + rz * rz < (m.r_c + 3.0 * s) * (m.r_c + 3.0 * s))
                 pair_moments_gh27<T>(m, cls, rx, ry, rz, s, out);  // only the 27-node rule comes here
+            static_assert(kPQ0 == 0 && kPQ1 == 0, "ratio kernels take the pipelined loop");
 #pragma unroll
             for (int v = 0; v < per; ++v) {
                 Vec16<T> b;
@@ -462,7 +516,7 @@ void k_pair(Dev d, Model m) {
             const Ends nxt = site_data(ia, ja);  // next pair's data (its indices arrived earlier)
             ends(p + 2 * kBS, ia, ja);           // indices two pairs ahead
             T out[kFBlk];
-            pair_all_moments<T, kRule>(m, S, cur.xj - cur.xi, cur.yj - cur.yi, cur.zj - cur.zi, cur.si, cur.sj,
+            pair_all_moments<T, kRule, kPQ0, kPQ1>(m, S, cur.xj - cur.xi, cur.yj - cur.yi, cur.zj - cur.zi, cur.si, cur.sj,
                                        p < pend ? pair_cls(cur.ti, cur.tj) : -1, out);
             if (p < pend) {
                 dblk[2 * p] = out[M_F];
@@ -834,13 +888,26 @@ __global__ __launch_bounds__(kChunk) void k_force_fold(Dev d) {
     }
 }
 
+template <typename T, int kRule, int kPQ0, int kPQ1>
+void launch_pair_q(const Dev& d, const Model& m, int bs, hipStream_t s) {
+    switch (bs) {
+        case 64: k_pair<T, 64, kRule, kPQ0, kPQ1><<<d.n_pchunks << m.pair_shift, 64, 0, s>>>(d, m); break;
+        case 128: k_pair<T, 128, kRule, kPQ0, kPQ1><<<d.n_pchunks << m.pair_shift, 128, 0, s>>>(d, m); break;
+        default: k_pair<T, 256, kRule, kPQ0, kPQ1><<<d.n_pchunks << m.pair_shift, 256, 0, s>>>(d, m); break;
+    }
+}
+
+// FP64 kernels compiled for the exponent ratios of the analytic EAM of the
+// synthetic workloads (host-host 8 : 6 = 4 : 3, host-interstitial 5 : 4);
+// any other potential takes the two-exponential kernel. FP32 node arithmetic
+// uses the hardware exp2 and keeps two exponentials.
 template <typename T, int kRule>
 void launch_pair_r(const Dev& d, const Model& m, int bs, hipStream_t s) {
-    switch (bs) {
-        case 64: k_pair<T, 64, kRule><<<d.n_pchunks << m.pair_shift, 64, 0, s>>>(d, m); break;
-        case 128: k_pair<T, 128, kRule><<<d.n_pchunks << m.pair_shift, 128, 0, s>>>(d, m); break;
-        default: k_pair<T, 256, kRule><<<d.n_pchunks << m.pair_shift, 256, 0, s>>>(d, m); break;
-    }
+    if (sizeof(T) == sizeof(double) && m.ratio_pq[0] == 0x43 && m.ratio_pq[1] == 0x54)
+        launch_pair_q<T, kRule, (sizeof(T) == sizeof(double) ? 0x43 : 0), (sizeof(T) == sizeof(double) ? 0x54 : 0)>(
+            d, m, bs, s);
+    else
+        launch_pair_q<T, kRule, 0, 0>(d, m, bs, s);
 }
 
 template <typename T>

@@ -101,6 +101,7 @@ struct Model {
     PolyCoef poly;
     int gather_stride;             // chunk visit stride of the gathers (xcd_unit_strided)
     int pair_shift;                // log2 of the pair-kernel blocks per pair chunk
+    int ratio_pq[2];               // per class: 16 P + Q when alpha : gamma = P : Q (P, Q <= 15), else 0
 };
 
 // Every device pointer the kernels use.

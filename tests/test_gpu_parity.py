@@ -85,6 +85,39 @@ def test_evaluate_is_deterministic(mx):
         assert torch.equal(getattr(out_a, n), getattr(out_b, n)), n
 
 
+# Exponents alpha, gamma per pair class (host-host, host-interstitial). The
+# synthetic potential's 8 : 6 and 5 : 4 take the FP64 kernels built on one
+# exponential per node (both shapes as powers of it); these take the kernel
+# with two exponentials: no small ratio, the ratios in one class only, and a
+# ratio no kernel is compiled for.
+OTHER_EXPONENTS = {
+    "no_ratio": ([7.3, 5.1], [6.2, 3.9]),
+    "class0_ratio_only": ([8.0, 5.2], [6.0, 4.0]),
+    "ratio_3_2": ([9.0, 5.0], [6.0, 4.0]),
+}
+
+
+@pytest.mark.parametrize("rule", [0, 1], ids=["gh27", "degree3"])
+@pytest.mark.parametrize("variant", list(OTHER_EXPONENTS))
+def test_evaluate_other_exponents(mx, variant, rule):
+    al, ga = OTHER_EXPONENTS[variant]
+    eam = dict(EAM, alpha=al, gamma=ga, quad_rule=rule)
+    for name, s in (parity_systems()[3], parity_systems()[2]):  # both pair classes; hosts only
+        say(f"[gpu] evaluate fp64 {variant} rule {rule} {name}")
+        plan = mx.Plan([s], eam, P, k_max=kmax_for([s]))
+        st, out, ws = plan.state([s]), plan.out(), plan.workspace()
+        plan.evaluate(st, out, ws)
+        torch.cuda.synchronize()
+        sc = plan.scalars(out)[0]
+        assert int(sc[mx.S_STATUS]) & mx.FATAL_STATUS == 0, sc
+        o = oracle_eval(eam, s)
+        errs = eval_errors(gpu_arrays(plan, st, out), o)
+        say(f"    errors {errs}")
+        for k, v in errs.items():
+            assert v < 1e-10, (k, v)
+        assert abs(sc[mx.S_F] - o["F"]) < 1e-10 * abs(o["F"])
+
+
 @pytest.mark.parametrize("name,s", parity_systems()[:4], ids=[n for n, _ in parity_systems()[:4]])
 def test_evaluate_fp32_mixed(mx, name, s):
     say(f"[gpu] evaluate fp32-mixed {name}")
