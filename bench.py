@@ -29,10 +29,12 @@ PEAK_HBM_GBS = 8000.0
 # FP64 vector: 256 CUs x 64 FP64 lanes/clock x 2.4 GHz = 39.3e12 lane-operations/s
 # (78.6 TFLOP/s counting a fused multiply-add as two flops).
 PEAK_FP64_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic work of one pair quadrature: 27 nodes x 90 FP64 operations (two
-# exponentials, square root, reciprocal, taper and ~30 multiply-adds for the
-# values, gradients and width derivatives of both radial shapes).
-OPS_PER_PAIR = 27 * 90
+# Algorithmic work of one pair quadrature: 27 nodes x 77 FP64 operations (one
+# exponential u and three multiplies for the two shapes' exponentials u^4 and
+# u^3, which the synthetic potential's exponent ratios allow; square root,
+# reciprocal, taper and ~30 multiply-adds for the values, gradients and width
+# derivatives of both radial shapes). Two exponentials would make it 90.
+OPS_PER_PAIR = 27 * 77
 # Algorithmic HBM bytes of the force/mu gather: each pair's 14 FP64 moments and
 # its row entry (neighbour index, pair id) are read from both ends; per site the
 # state, embedding terms, FIRE velocity and the six outputs.
@@ -56,10 +58,10 @@ BREAKDOWN_STEPS = 2
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="512c6dc1414a5178",
-    pair=dict(fetch_kib=71056.4, write_kib=1019787.0),
-    force=dict(fetch_kib=896894.8, write_kib=13693.8),
-    density=dict(fetch_kib=137325.6, write_kib=27109.7),
+    sources_sha256_16="873e06ff00340ab6",
+    pair=dict(fetch_kib=70451.0, write_kib=1019787.0),
+    force=dict(fetch_kib=896910.4, write_kib=13675.4),
+    density=dict(fetch_kib=137317.6, write_kib=27124.7),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -78,11 +80,11 @@ def counter_traffic(family: str):
 # VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
 # Valid only for the sources they were taken on.
 VALU_COUNTERS = dict(
-    sources_sha256_16="512c6dc1414a5178",
-    pair=dict(SQ_INSTS_VALU=226718612.5, SQ_INSTS_VALU_FMA_F64=121839303.8,
-              SQ_INSTS_VALU_MUL_F64=29613988.7, SQ_INSTS_VALU_ADD_F64=12554662.7,
-              SQ_INSTS_VALU_TRANS_F64=3222596.6, SQ_INSTS_VALU_FLOPS_FP64=289069864.3,
-              VALUBusy=71.80, VALUUtilization=90.36),
+    sources_sha256_16="873e06ff00340ab6",
+    pair=dict(SQ_INSTS_VALU=200138209.7, SQ_INSTS_VALU_FMA_F64=90583810.2,
+              SQ_INSTS_VALU_MUL_F64=39740249.2, SQ_INSTS_VALU_ADD_F64=9895150.5,
+              SQ_INSTS_VALU_TRANS_F64=3332416.7, SQ_INSTS_VALU_FLOPS_FP64=234134839.2,
+              VALUBusy=69.23, VALUUtilization=89.28),
 )
 
 
@@ -656,7 +658,7 @@ def main():
     roof_pair = dict(bound="alu", achieved=ops / pair_avg_s / 1e12 if pair_avg_s > 0 else 0.0,
                      peak=PEAK_FP64_TOPS, unit="Tops/s", kernel="k_pair<double>",
                      traffic=counter_traffic("pair"), traffic_unit="B/launch",
-                     work="algorithmic: 27 nodes x 90 FP64 operations per listed pair "
+                     work="algorithmic: 27 nodes x 77 FP64 operations per listed pair "
                           "(nominal count, not the executed instructions)")
     roof_pair["frac"] = roof_pair["achieved"] / roof_pair["peak"]
     valu = valu_counters(pair_avg_s)
