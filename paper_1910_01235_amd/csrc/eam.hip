@@ -131,7 +131,12 @@ template <typename T, int kPQ = 0, int kPQ1 = kPQ>
 __device__ inline ShapeK<T> shape_consts(const Model& m, int cls) {
     constexpr double kLog2e = 1.4426950408889634;
     constexpr double kPi = 3.141592653589793;
-    const double ir = m.inv_re[cls], al = m.alpha[cls], ga = m.gamma[cls], tw = m.taper_inv_w;
+    // selected from both classes' values rather than indexed by the per-lane
+    // class: an indexed kernel argument is a vector load whose wait would also
+    // wait for the pair data the loop prefetches
+    const bool c1 = cls != 0;
+    const double ir = c1 ? m.inv_re[1] : m.inv_re[0], al = c1 ? m.alpha[1] : m.alpha[0];
+    const double ga = c1 ? m.gamma[1] : m.gamma[0], tw = m.taper_inv_w;
     ShapeK<T> k;
     k.p1 = (T)(-al * ir * kLog2e);
     k.p0 = (T)(al * kLog2e);
@@ -394,10 +399,27 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
     }
 }
 
-__device__ inline void min_image(const SysDesc& S, double& dx, double& dy, double& dz) {
-    if (S.periodic[0]) dx -= S.box[0] * rint(dx / S.box[0]);
-    if (S.periodic[1]) dy -= S.box[1] * rint(dy / S.box[1]);
-    if (S.periodic[2]) dz -= S.box[2] * rint(dz / S.box[2]);
+// A system's periodic box, copied into registers before a pair loop: read
+// through the system record inside the loop, the compiler reloads it after
+// every store (it may alias) and waits for every load in flight.
+struct Box {
+    double len[3];
+    bool periodic[3];
+};
+
+__device__ inline Box box_of(const SysDesc& S) {
+    Box b;
+    for (int k = 0; k < 3; ++k) {
+        b.len[k] = S.box[k];
+        b.periodic[k] = S.periodic[k] != 0;
+    }
+    return b;
+}
+
+__device__ inline void min_image(const Box& B, double& dx, double& dy, double& dz) {
+    if (B.periodic[0]) dx -= B.len[0] * rint(dx / B.len[0]);
+    if (B.periodic[1]) dy -= B.len[1] * rint(dy / B.len[1]);
+    if (B.periodic[2]) dz -= B.len[2] * rint(dz / B.len[2]);
 }
 
 }  // namespace
@@ -415,11 +437,11 @@ struct alignas(16) Vec16 {
 // (host-host, host-interstitial), served by one body (two bodies in one
 // loop spill at the FP64 kernels' 128 VGPRs).
 template <typename T, int kRule, int kPQ0 = 0, int kPQ1 = 0>
-__device__ inline void pair_all_moments(const Model& m, const SysDesc& S, double rx, double ry,
+__device__ inline void pair_all_moments(const Model& m, const Box& B, double rx, double ry,
                                         double rz, double si, double sj, int cls, T out[kFBlk]) {
 #pragma unroll
     for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
-    min_image(S, rx, ry, rz);
+    min_image(B, rx, ry, rz);
     const double s = sqrt(si * si + sj * sj);
     // a pair contributes iff some node lies inside r_c: the farthest node is
     // 3 s from rbar under the product rule, sqrt(6) max(sigma) under degree 3
@@ -455,6 +477,7 @@ void k_pair(Dev d, Model m) {
     const SysCtl& c = d.ctl[ch.sys];
     if (c.done) return;  // uniform over the block
     const SysDesc& S = d.sys[ch.sys];
+    const Box B = box_of(S);
     const int64_t sub = kPairChunk >> m.pair_shift;
     const int64_t cstart = ch.start + (int64_t)(blockIdx.x & ((1u << m.pair_shift) - 1)) * sub;
     const int64_t pend =
@@ -466,7 +489,7 @@ void k_pair(Dev d, Model m) {
         for (int64_t p = cstart + threadIdx.x; p < pend; p += blockDim.x) {
             const int i = d.pair_i[p], j = d.pair_j[p];
             double rx = d.qx[j] - d.qx[i], ry = d.qy[j] - d.qy[i], rz = d.qz[j] - d.qz[i];
-            min_image(S, rx, ry, rz);
+            min_image(B, rx, ry, rz);
             const double si = d.sigma[i], sj = d.sigma[j];
             const double s = sqrt(si * si + sj * sj);
             const int cls = pair_cls(d.type[i], d.type[j]);
@@ -511,13 +534,25 @@ void k_pair(Dev d, Model m) {
         ends(p0, ia, ja);
         Ends cur = site_data(ia, ja);
         ends(p0 + kBS, ia, ja);  // indices of the next pair
+        // the loop head uses the next pair's indices, arrived either here or
+        // before the previous batch's stores: with this wait both ways in
+        // agree, and the head waits for nothing (it would else wait for the
+        // stores in flight, see below)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         for (int64_t base = cstart; base < pend; base += kBS) {  // uniform over the block
             const int64_t p = base + threadIdx.x;
             const Ends nxt = site_data(ia, ja);  // next pair's data (its indices arrived earlier)
             ends(p + 2 * kBS, ia, ja);           // indices two pairs ahead
             T out[kFBlk];
-            pair_all_moments<T, kRule, kPQ0, kPQ1>(m, S, cur.xj - cur.xi, cur.yj - cur.yi, cur.zj - cur.zi, cur.si, cur.sj,
+            pair_all_moments<T, kRule, kPQ0, kPQ1>(m, B, cur.xj - cur.xi, cur.yj - cur.yi, cur.zj - cur.zi, cur.si, cur.sj,
                                        p < pend ? pair_cls(cur.ti, cur.tj) : -1, out);
+            // Loads and stores share one counter and may complete out of order,
+            // so any wait for a load while stores are in flight waits for all of
+            // them. The prefetched loads have long arrived by now and the
+            // previous batch's stores are a whole quadrature old: wait here,
+            // before this batch's stores, and nothing the next batch needs is
+            // in flight behind them (vmcnt 0; expcnt and lgkmcnt not waited on).
+            __builtin_amdgcn_s_waitcnt(0x0F70);
             if (p < pend) {
                 dblk[2 * p] = out[M_F];
                 dblk[2 * p + 1] = out[M_F0];
@@ -606,12 +641,18 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
         rb = group_sum<kLPS>(rb);
         r0 = group_sum<kLPS>(r0);
         if (sub == 0) {
+            // (the per-species tables are indexed by the site's species and
+            // loads follow stores here: each such load's wait also waits for
+            // the stores in flight, yet the forms without those waits, as in
+            // the force gather, measured slower in this kernel: 150 -> 156-159
+            // us on the 256k-site vacancy crystal)
             const int ti = d.type[i];
             const double xi = d.x[i];
             d.rho_bar[i] = rb;
             d.rho0[i] = r0;
             // the embedding share c_i G_i carries the site's weight theta_i = T / T_i
-            const double th = theta_at(d, d.sys[ch.sys], i);
+            const double th = theta_at(d, d.sys[ch.sys].T, i);
+            const double emit_i = d.emit[i];
             double G = 0.0, A = 0.0, B = 0.0;
             const bool embeds = m.c4[occ_sp1(ti)] != 0.0 || m.c4[occ_sp0(ti)] != 0.0;
             if (embeds) {
@@ -619,7 +660,7 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
                     // F~(rho) = -sqrt(rho): F~' = -1/(2 sqrt rho), F~'' = 1/(4 rho^1.5)
                     const double sq = sqrt(r0);
                     const double F1 = -0.5 / sq, F2 = 0.25 / (sq * r0);
-                    const double ch_i = mixhat(m.c4, ti, xi);
+                    const double ch_i = mixhat_indexed(m.c4, ti, xi);
                     G = -sq + F1 * (rb - r0);
                     A = th * ch_i * F1;
                     B = th * ch_i * F2 * (rb - r0);
@@ -640,7 +681,7 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
             T* R = (T*)d.srec + (int64_t)i * kSRec;
             R[0] = (T)(w * A);
             R[1] = (T)(w * B);
-            R[2] = (T)d.emit[i];
+            R[2] = (T)emit_i;
             for (int k = 0; k < 3; ++k) R[3 + k] = (T)(p1 * m.a4[k][s1] + (1.0 - p1) * m.a4[k][s0]);
             R[6] = (T)th;
             R[7] = T(0);
@@ -684,7 +725,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int sys = ch.sys;
     if (d.ctl[sys].done) return;
     const SysDesc& S = d.sys[sys];
-    const double kT = S.kT;
+    const double kT = S.kT, T_sys = S.T;
     const bool site_T = d.T_site != nullptr;
     const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
     constexpr int kQL = kQ<T>;                // lanes per entry
@@ -697,6 +738,13 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
     double pe = 0.0, pfmax = 0.0, pfv = 0.0, pff = 0.0, pvv = 0.0, psx = 0.0;
     int bad = 0;
     for (int i = i_lo + grp; i < i_hi; i += kGroups) {
+        // the site's loads, and its first row entry's, in one round trip (the
+        // entry loaded unconditionally, its index clamped into the row)
+        const int cnt = d.nbr_cnt[i];
+        const int* row = d.nbr + (int64_t)i * K;
+        const int* prow = d.pid + (int64_t)i * K;
+        const int e0 = min(es, K - 1);
+        const int j0 = row[e0], p0 = prow[e0];
         const int ti = d.type[i];
         const double xi = d.x[i], si = d.sigma[i];
         const double Ahi = d.Ahat[i], Bhi = d.Bhat[i];
@@ -704,18 +752,11 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int i1 = occ_sp1(ti), i0 = occ_sp0(ti);
         const double bhat_i = mixhat(m.b4, ti, xi), db_i = mixdx(m.b4, ti);
         const bool part_i = occ_partial(ti), mob_i = occ_mobile(ti);
-        const double th_i = theta_at(d, S, i);
-        const int cnt = d.nbr_cnt[i];
-        const int* row = d.nbr + (int64_t)i * K;
-        const int* prow = d.pid + (int64_t)i * K;
+        const double th_i = theta_at(d, T_sys, i);
         double fx = 0.0, fy = 0.0, fz = 0.0, fsg = 0.0, mu = 0.0, ep = 0.0;
         // the next entry's (j, pair id) load while this entry's block and record
         // are fetched, so an iteration waits for one round trip instead of three
-        int jn = 0, pn = -1;
-        if (es < cnt) {
-            jn = row[es];
-            pn = prow[es];
-        }
+        int jn = es < cnt ? j0 : 0, pn = es < cnt ? p0 : -1;
         for (int k = es; k < cnt; k += kLPS / kQL) {
             const int j = jn, p = pn;
             if (k + kLPS / kQL < cnt) {
@@ -800,7 +841,10 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
         mu = group_sum<kLPS>(mu);
         ep = group_sum<kLPS>(ep);
         if (sub == 0) {
+            // every load before the first store (a load issued behind stores
+            // waits for them)
             const double Gi = d.G[i];
+            const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i], vs = d.vs[i];
             const double lns = log(si);
             const double fs = -si * fsg + 3.0 * kT / si;
             const double wi = part_i ? xi : 1.0;
@@ -820,7 +864,6 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
             d.fs[i] = fs;
             d.mu[i] = mui;
             d.e_site[i] = ei;
-            const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i], vs = d.vs[i];
             pe += ei;
             psx += xi;
             pfmax = fmax(pfmax, fmax(fmax(fabs(fx), fabs(fy)), fmax(fabs(fz), fabs(fs))));

@@ -155,8 +155,9 @@ __host__ __device__ inline int occ_sp0(int t) { return t == MXE_SITE_ALLOY ? 0 :
 __host__ __device__ inline double occ_p1(int t, double x) { return t == MXE_SITE_HOST_FIXED ? 1.0 : x; }
 __host__ __device__ inline bool occ_mobile(int t) { return t != MXE_SITE_HOST_FIXED; }
 // weight of site i's energy share, T / T_i (1 at uniform temperature)
-__device__ inline double theta_at(const Dev& d, const SysDesc& S, int i) {
-    return d.T_site != nullptr ? S.T / d.T_site[i] : 1.0;
+// (T_sys: the system's reference temperature, read once before a site loop)
+__device__ inline double theta_at(const Dev& d, double T_sys, int i) {
+    return d.T_site != nullptr ? T_sys / d.T_site[i] : 1.0;
 }
 
 // Running maximum of non-negative doubles kept as their bit patterns (ordered
@@ -205,17 +206,41 @@ __host__ __device__ inline int pair_cls(int ti, int tj) {
     return (a && b) ? -1 : ((a || b) ? 1 : 0);
 }
 
+// A value that is the same on every lane (a kernel argument), passed through
+// readfirstlane: it stays in scalar registers, and a select between such
+// values stays a select instead of becoming one load from a selected address.
+__device__ inline double uniform_value(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+// v4[k] of a per-species table in the kernel arguments (the same on every
+// lane), for a per-lane k, selected from the four values: indexed by a lane's
+// value, the table would be read with a vector load, and waiting for that
+// load waits for every load and store the thread has in flight.
+__device__ inline double sp4(const double* v4, int k) {
+    const double v0 = uniform_value(v4[0]), v1 = uniform_value(v4[1]);
+    const double v2 = uniform_value(v4[2]), v3 = uniform_value(v4[3]);
+    const double a = k == 1 ? v1 : v0;
+    const double b = k == 3 ? v3 : v2;
+    return k < 2 ? a : b;
+}
 // per-species value mixed by the site's occupancy
 __device__ inline double mixval(const double* v4, int t, double x) {
     const double p = occ_p1(t, x);
-    return p * v4[occ_sp1(t)] + (1.0 - p) * v4[occ_sp0(t)];
+    return p * sp4(v4, occ_sp1(t)) + (1.0 - p) * sp4(v4, occ_sp0(t));
 }
 // the same divided by the vibrating fraction w (closed form)
 __device__ inline double mixhat(const double* v4, int t, double x) {
-    return occ_partial(t) ? v4[occ_sp1(t)] : mixval(v4, t, x);
+    return occ_partial(t) ? sp4(v4, occ_sp1(t)) : mixval(v4, t, x);
 }
 __device__ inline double mixdx(const double* v4, int t) {
-    return occ_mobile(t) ? v4[occ_sp1(t)] - v4[occ_sp0(t)] : 0.0;
+    return occ_mobile(t) ? sp4(v4, occ_sp1(t)) - sp4(v4, occ_sp0(t)) : 0.0;
+}
+// mixhat with the table indexed by the lane's species (the same value)
+__device__ inline double mixhat_indexed(const double* v4, int t, double x) {
+    const double p = occ_p1(t, x);
+    return occ_partial(t) ? v4[occ_sp1(t)] : p * v4[occ_sp1(t)] + (1.0 - p) * v4[occ_sp0(t)];
 }
 
 // index ranges for grid-stride loops
