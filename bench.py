@@ -52,16 +52,16 @@ BREAKDOWN_STEPS = 2
 
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
 # this bench (--steps 2 --warmup 1 --no-extras --no-cpu-baseline --calib-copy
-# --shapes gather_lanes=8,force_lanes=16,pair_block=256,pair_split=8,gather_stride=26),
+# --shapes gather_lanes=8,force_lanes=16,pair_block=256,pair_split=2,gather_stride=26),
 # KiB per dispatch averaged over the run's dispatches, scaled by what the same
 # counters read for a 1 GiB device copy (FETCH x 2, WRITE x 1). Valid only for
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="873e06ff00340ab6",
-    pair=dict(fetch_kib=70451.0, write_kib=1019787.0),
-    force=dict(fetch_kib=896910.4, write_kib=13675.4),
-    density=dict(fetch_kib=137317.6, write_kib=27124.7),
+    sources_sha256_16="e31a3079476becb7",
+    pair=dict(fetch_kib=147552.7, write_kib=1019787.0),
+    force=dict(fetch_kib=903466.7, write_kib=14124.7),
+    density=dict(fetch_kib=137344.6, write_kib=27148.9),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -80,11 +80,11 @@ def counter_traffic(family: str):
 # VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
 # Valid only for the sources they were taken on.
 VALU_COUNTERS = dict(
-    sources_sha256_16="873e06ff00340ab6",
-    pair=dict(SQ_INSTS_VALU=200138209.7, SQ_INSTS_VALU_FMA_F64=90583810.2,
-              SQ_INSTS_VALU_MUL_F64=39740249.2, SQ_INSTS_VALU_ADD_F64=9895150.5,
-              SQ_INSTS_VALU_TRANS_F64=3332416.7, SQ_INSTS_VALU_FLOPS_FP64=234134839.2,
-              VALUBusy=69.23, VALUUtilization=89.28),
+    sources_sha256_16="e31a3079476becb7",
+    pair=dict(SQ_INSTS_VALU=208533699.3, SQ_INSTS_VALU_FMA_F64=90583698.8,
+              SQ_INSTS_VALU_MUL_F64=39612746.6, SQ_INSTS_VALU_ADD_F64=9895163.1,
+              SQ_INSTS_VALU_TRANS_F64=3332431.1, SQ_INSTS_VALU_FLOPS_FP64=234008142.0,
+              VALUBusy=84.10, VALUUtilization=85.39),
 )
 
 

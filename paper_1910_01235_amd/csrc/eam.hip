@@ -546,9 +546,11 @@ void k_pair(Dev d, Model m) {
             T out[kFBlk];
             pair_all_moments<T, kRule, kPQ0, kPQ1>(m, B, cur.xj - cur.xi, cur.yj - cur.yi, cur.zj - cur.zi, cur.si, cur.sj,
                                        p < pend ? pair_cls(cur.ti, cur.tj) : -1, out);
-            // Loads and stores share one counter and may complete out of order,
-            // so any wait for a load while stores are in flight waits for all of
-            // them. The prefetched loads have long arrived by now and the
+            // Loads and stores share one counter: a wait for a load also waits
+            // for everything issued before it, and where the compiler cannot
+            // count what was issued after it (the store loop below has a
+            // variable trip count) it waits for everything, this batch's stores
+            // included. The prefetched loads have long arrived by now and the
             // previous batch's stores are a whole quadrature old: wait here,
             // before this batch's stores, and nothing the next batch needs is
             // in flight behind them (vmcnt 0; expcnt and lgkmcnt not waited on).
