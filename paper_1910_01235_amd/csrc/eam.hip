@@ -457,17 +457,15 @@ __device__ inline void pair_all_moments(const Model& m, const Box& B, double rx,
 template <typename T, int kBS, int kRule, int kPQ0 = 0, int kPQ1 = 0>
 __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1)))
 void k_pair(Dev d, Model m) {
-    // Two latency measures, used where they measured faster (the FP64 kernels
-    // and the degree-3 rule; the FP32 27-node kernel, already at high
-    // occupancy, keeps the plain loop and stores):
+    // Two latency measures:
     //  * a software pipeline of the pair data: the endpoint indices are loaded
     //    two pairs ahead and the endpoints' positions, widths and types one
     //    pair ahead, so the quadrature of a pair never waits for the dependent
     //    loads of its own data;
-    //  * a thread's 16 moments are staged in LDS and the block writes its kBS
-    //    consecutive force blocks as one contiguous range, 16 B per lane and
-    //    store, so a store covers whole cache lines instead of 16 B of 64 lines.
-    constexpr bool kPipe = sizeof(T) == sizeof(double) || kRule == MXE_QUAD_DEGREE3;
+    //  * a thread's 16 moments are staged in LDS and written back as
+    //    contiguous ranges of force blocks (a wavefront's 64, or the block's
+    //    kBS), 16 B per lane and store, so a store covers whole cache lines
+    //    instead of 16 B of 64 lines.
     constexpr int per = kFBlk / Vec16<T>::n;  // vectors per force block
     constexpr int kRow = per + 1;             // LDS row (odd stride against bank conflicts)
     // pair chunks are sized to capacity and only the leading ones are active,
@@ -485,93 +483,85 @@ void k_pair(Dev d, Model m) {
     Vec16<T>* fblk = (Vec16<T>*)d.fblk;
     T* dblk = (T*)d.dblk;
 
-    if constexpr (!kPipe) {
-        for (int64_t p = cstart + threadIdx.x; p < pend; p += blockDim.x) {
-            const int i = d.pair_i[p], j = d.pair_j[p];
-            double rx = d.qx[j] - d.qx[i], ry = d.qy[j] - d.qy[i], rz = d.qz[j] - d.qz[i];
-            min_image(B, rx, ry, rz);
-            const double si = d.sigma[i], sj = d.sigma[j];
-            const double s = sqrt(si * si + sj * sj);
-            const int cls = pair_cls(d.type[i], d.type[j]);
-            T out[kFBlk];
-#pragma unroll
-            for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
-            if (cls >= 0 && rx * rx + ry * ry + rz * rz < (m.r_c + 3.0 * s) * (m.r_c + 3.0 * s))
-                pair_moments_gh27<T>(m, cls, rx, ry, rz, s, out);  // only the 27-node rule comes here
-            static_assert(kPQ0 == 0 && kPQ1 == 0, "ratio kernels take the pipelined loop");
-#pragma unroll
-            for (int v = 0; v < per; ++v) {
-                Vec16<T> b;
-#pragma unroll
-                for (int e = 0; e < Vec16<T>::n; ++e) b.v[e] = out[v * Vec16<T>::n + e];
-                fblk[p * per + v] = b;
-            }
+    // a pair past the chunk end reads site 0 (always present) and computes nothing
+    __shared__ Vec16<T> stage[kBS * kRow];
+    auto ends = [&](int64_t q, int& a, int& b) {
+        a = 0;
+        b = 0;
+        if (q < pend) {
+            a = d.pair_i[q];
+            b = d.pair_j[q];
+        }
+    };
+    struct Ends {
+        double xi, yi, zi, si, xj, yj, zj, sj;
+        int ti, tj;
+    };
+    auto site_data = [&](int a, int b) {
+        return Ends{d.qx[a], d.qy[a], d.qz[a], d.sigma[a], d.qx[b], d.qy[b], d.qz[b], d.sigma[b],
+                    (int)d.type[a], (int)d.type[b]};
+    };
+    const int64_t p0 = cstart + threadIdx.x;
+    int ia, ja;
+    ends(p0, ia, ja);
+    Ends cur = site_data(ia, ja);
+    ends(p0 + kBS, ia, ja);  // indices of the next pair
+    // the loop head uses the next pair's indices, arrived either here or
+    // before the previous batch's stores: with this wait both ways in
+    // agree, and the head waits for nothing (it would else wait for the
+    // stores in flight, see below)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    for (int64_t base = cstart; base < pend; base += kBS) {  // uniform over the block
+        const int64_t p = base + threadIdx.x;
+        const Ends nxt = site_data(ia, ja);  // next pair's data (its indices arrived earlier)
+        ends(p + 2 * kBS, ia, ja);           // indices two pairs ahead
+        T out[kFBlk];
+        pair_all_moments<T, kRule, kPQ0, kPQ1>(m, B, cur.xj - cur.xi, cur.yj - cur.yi, cur.zj - cur.zi, cur.si,
+                                               cur.sj, p < pend ? pair_cls(cur.ti, cur.tj) : -1, out);
+        // Loads and stores share one counter: a wait for a load also waits
+        // for everything issued before it, and where the compiler cannot
+        // count what was issued after it (the store loop below has a
+        // variable trip count) it waits for everything, this batch's stores
+        // included. The prefetched loads have long arrived by now and the
+        // previous batch's stores are a whole quadrature old: wait here,
+        // before this batch's stores, and nothing the next batch needs is
+        // in flight behind them (vmcnt 0; expcnt and lgkmcnt not waited on).
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        if (p < pend) {
             dblk[2 * p] = out[M_F];
             dblk[2 * p + 1] = out[M_F0];
         }
-    } else {
-        // pipelined loop; a pair past the chunk end reads site 0 (always present)
-        // and computes nothing
-        __shared__ Vec16<T> stage[kBS * kRow];
-        auto ends = [&](int64_t q, int& a, int& b) {
-            a = 0;
-            b = 0;
-            if (q < pend) {
-                a = d.pair_i[q];
-                b = d.pair_j[q];
-            }
-        };
-        struct Ends {
-            double xi, yi, zi, si, xj, yj, zj, sj;
-            int ti, tj;
-        };
-        auto site_data = [&](int a, int b) {
-            return Ends{d.qx[a], d.qy[a], d.qz[a], d.sigma[a], d.qx[b], d.qy[b], d.qz[b], d.sigma[b],
-                        (int)d.type[a], (int)d.type[b]};
-        };
-        const int64_t p0 = cstart + threadIdx.x;
-        int ia, ja;
-        ends(p0, ia, ja);
-        Ends cur = site_data(ia, ja);
-        ends(p0 + kBS, ia, ja);  // indices of the next pair
-        // the loop head uses the next pair's indices, arrived either here or
-        // before the previous batch's stores: with this wait both ways in
-        // agree, and the head waits for nothing (it would else wait for the
-        // stores in flight, see below)
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        for (int64_t base = cstart; base < pend; base += kBS) {  // uniform over the block
-            const int64_t p = base + threadIdx.x;
-            const Ends nxt = site_data(ia, ja);  // next pair's data (its indices arrived earlier)
-            ends(p + 2 * kBS, ia, ja);           // indices two pairs ahead
-            T out[kFBlk];
-            pair_all_moments<T, kRule, kPQ0, kPQ1>(m, B, cur.xj - cur.xi, cur.yj - cur.yi, cur.zj - cur.zi, cur.si, cur.sj,
-                                       p < pend ? pair_cls(cur.ti, cur.tj) : -1, out);
-            // Loads and stores share one counter: a wait for a load also waits
-            // for everything issued before it, and where the compiler cannot
-            // count what was issued after it (the store loop below has a
-            // variable trip count) it waits for everything, this batch's stores
-            // included. The prefetched loads have long arrived by now and the
-            // previous batch's stores are a whole quadrature old: wait here,
-            // before this batch's stores, and nothing the next batch needs is
-            // in flight behind them (vmcnt 0; expcnt and lgkmcnt not waited on).
-            __builtin_amdgcn_s_waitcnt(0x0F70);
-            if (p < pend) {
-                dblk[2 * p] = out[M_F];
-                dblk[2 * p + 1] = out[M_F0];
-            }
 #pragma unroll
-            for (int v = 0; v < per; ++v) {
-                Vec16<T> b;
+        for (int v = 0; v < per; ++v) {
+            Vec16<T> b;
 #pragma unroll
-                for (int e = 0; e < Vec16<T>::n; ++e) b.v[e] = out[v * Vec16<T>::n + e];
-                stage[threadIdx.x * kRow + v] = b;
-            }
+            for (int e = 0; e < Vec16<T>::n; ++e) b.v[e] = out[v * Vec16<T>::n + e];
+            stage[threadIdx.x * kRow + v] = b;
+        }
+        // (not the FP64 two-exponential 27-node kernel: there it spills at 128 VGPRs)
+        if constexpr (kRule == MXE_QUAD_GH27 && (kPQ0 != 0 || sizeof(T) == sizeof(float))) {
+            // each wavefront writes its own 64 blocks (one contiguous range):
+            // no block barrier, as a wavefront's LDS operations execute in
+            // order (the wave barriers only keep the compiler from moving LDS
+            // accesses across); the loop stays rolled, as unrolled the
+            // compiler waits for each store before reusing its data register
+            __builtin_amdgcn_wave_barrier();
+            const int w0 = (int)(threadIdx.x & ~(kWave - 1)), ln = (int)(threadIdx.x & (kWave - 1));
+            const int64_t wb = base + w0;
+            const int nw = (int)max((int64_t)0, min((int64_t)kWave, pend - wb));
+#pragma unroll 1
+            for (int q = ln; q < nw * per; q += kWave) fblk[wb * per + q] = stage[(w0 + q / per) * kRow + q % per];
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            // the degree-3 kernels measured faster writing block-wide
+            // (FP64 0.293 against 0.304 ms, FP32 0.178 against 0.192 ms on the
+            // 256k-site vacancy crystal)
             __syncthreads();
             const int nb = (int)min((int64_t)kBS, pend - base);  // pairs of this batch
             for (int q = threadIdx.x; q < nb * per; q += kBS) fblk[base * per + q] = stage[(q / per) * kRow + q % per];
             __syncthreads();  // the stage is rewritten by the next batch
-            cur = nxt;
         }
+        cur = nxt;
     }
 }
 
