@@ -453,9 +453,11 @@ __device__ inline void pair_all_moments(const Model& m, const Box& B, double rx,
 }
 
 // The FP64 kernels are held at 128 VGPRs (4 waves per SIMD): the 27-node
-// kernel's node sums would otherwise take 131 and drop to 3 waves.
+// kernel's node sums would otherwise take 131 and drop to 3 waves. The FP32
+// ones at 5 waves (the two-exponential 27-node kernel would take 110 VGPRs,
+// 4 waves: 0.249 -> 0.241 ms at 5 on the 256k-site vacancy crystal).
 template <typename T, int kBS, int kRule, int kPQ0 = 0, int kPQ1 = 0>
-__global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1)))
+__global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 5)))
 void k_pair(Dev d, Model m) {
     // Two latency measures:
     //  * a software pipeline of the pair data: the endpoint indices are loaded
@@ -932,15 +934,13 @@ void launch_pair_q(const Dev& d, const Model& m, int bs, hipStream_t s) {
     }
 }
 
-// FP64 kernels compiled for the exponent ratios of the analytic EAM of the
+// Kernels compiled for the exponent ratios of the analytic EAM of the
 // synthetic workloads (host-host 8 : 6 = 4 : 3, host-interstitial 5 : 4);
-// any other potential takes the two-exponential kernel. FP32 node arithmetic
-// uses the hardware exp2 and keeps two exponentials.
+// any other potential takes the two-exponential kernel.
 template <typename T, int kRule>
 void launch_pair_r(const Dev& d, const Model& m, int bs, hipStream_t s) {
-    if (sizeof(T) == sizeof(double) && m.ratio_pq[0] == 0x43 && m.ratio_pq[1] == 0x54)
-        launch_pair_q<T, kRule, (sizeof(T) == sizeof(double) ? 0x43 : 0), (sizeof(T) == sizeof(double) ? 0x54 : 0)>(
-            d, m, bs, s);
+    if (m.ratio_pq[0] == 0x43 && m.ratio_pq[1] == 0x54)
+        launch_pair_q<T, kRule, 0x43, 0x54>(d, m, bs, s);
     else
         launch_pair_q<T, kRule, 0, 0>(d, m, bs, s);
 }
