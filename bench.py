@@ -58,10 +58,10 @@ BREAKDOWN_STEPS = 2
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="928c75a1b4128537",
-    pair=dict(fetch_kib=130071.9, write_kib=1019787.0),
-    force=dict(fetch_kib=903493.7, write_kib=14137.7),
-    density=dict(fetch_kib=137340.7, write_kib=27128.3),
+    sources_sha256_16="7391f20978208f2c",
+    pair=dict(fetch_kib=129483.6, write_kib=1019787.0),
+    force=dict(fetch_kib=903346.2, write_kib=14136.0),
+    density=dict(fetch_kib=137329.9, write_kib=27126.5),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -80,11 +80,11 @@ def counter_traffic(family: str):
 # VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
 # Valid only for the sources they were taken on.
 VALU_COUNTERS = dict(
-    sources_sha256_16="928c75a1b4128537",
-    pair=dict(SQ_INSTS_VALU=209611089.9, SQ_INSTS_VALU_FMA_F64=90584118.8,
-              SQ_INSTS_VALU_MUL_F64=39612916.3, SQ_INSTS_VALU_ADD_F64=9895224.9,
-              SQ_INSTS_VALU_TRANS_F64=3332443.9, SQ_INSTS_VALU_FLOPS_FP64=234009754.5,
-              VALUBusy=84.72, VALUUtilization=85.48),
+    sources_sha256_16="7391f20978208f2c",
+    pair=dict(SQ_INSTS_VALU=209610810.1, SQ_INSTS_VALU_FMA_F64=90583941.8,
+              SQ_INSTS_VALU_MUL_F64=39612898.6, SQ_INSTS_VALU_ADD_F64=9895217.1,
+              SQ_INSTS_VALU_TRANS_F64=3332431.1, SQ_INSTS_VALU_FLOPS_FP64=234009296.5,
+              VALUBusy=85.75, VALUUtilization=85.49),
 )
 
 
