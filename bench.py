@@ -40,6 +40,10 @@ OPS_PER_PAIR = 27 * 77
 # state, embedding terms, FIRE velocity and the six outputs.
 BYTES_FORCE_PER_PAIR = 2 * (14 * 8 + 8)
 BYTES_FORCE_PER_SITE = 8 + 8 + 1 + 8 * 3 + 8 * 4 + 8 * 6
+# The same gather priced with each unordered pair's 14 FP64 moments read once
+# (the moment stream's own size): the gather reads each block from both ends,
+# so against this count it can reach at most about half of HBM peak.
+BYTES_FORCE_ONCE_PER_PAIR = 14 * 8
 # Algorithmic HBM bytes of the density gather: each pair's (<f>, f0) and row entry
 # read from both ends and the neighbour's emission; per site its row count, x,
 # type and the five outputs (rho_bar, rho0, G, A~, B~) plus the packed record.
@@ -675,6 +679,13 @@ def main():
                       work="each pair's 14 moments and row entry read from both ends, plus "
                            "per-site state, embedding terms and outputs")
     roof_force["frac"] = roof_force["achieved"] / roof_force["peak"]
+    bytes_once = (BYTES_FORCE_ONCE_PER_PAIR * pair_evals_b / max(evals_b, 1) + BYTES_FORCE_PER_SITE * n) \
+        * evals_per_launch
+    roof_force["once_per_pair"] = dict(
+        algorithmic_bytes=bytes_once,
+        achieved=bytes_once / force_avg_s / 1e9 if force_avg_s > 0 else 0.0,
+        frac=bytes_once / force_avg_s / 1e9 / PEAK_HBM_GBS if force_avg_s > 0 else 0.0,
+        work="each unordered pair's 14 moments counted once (112 B), plus the per-site bytes")
     bytes_dens = (BYTES_DENSITY_PER_PAIR * pair_evals_b / max(evals_b, 1) + BYTES_DENSITY_PER_SITE * n) \
         * evals_b / max(fam["density"]["launches"], 1)
     dens_avg_s = fam["density"]["ms_avg"] / 1e3
