@@ -66,14 +66,19 @@ struct mxe_plan {
     // prefix (rounded up to a power of two)
     int64_t live_chunks = 0, live_pchunks = 0;
     // graph cache for mxe_run, per buffers and launch extents: one diffusion
-    // step, or (relax_chunk > 0) a chunk of relaxation iterations and the Euler step
+    // step, or (relax_chunk > 0) a chunk of lean relaxation iterations, one
+    // iteration with the build chain and the Euler step; mxe_advance's chunk
+    // of lean free-running iterations and its iteration with the chain
     struct Graphs {
-        hipGraphExec_t step = nullptr, chunk = nullptr, master = nullptr, advance = nullptr;
+        hipGraphExec_t step = nullptr, chunk = nullptr, full = nullptr, master = nullptr, advance = nullptr,
+                       advance_full = nullptr;
+        std::vector<hipGraphExec_t> all() const { return {step, chunk, full, master, advance, advance_full}; }
     };
     hipStream_t cap_stream = nullptr;
     std::map<std::vector<const void*>, Graphs> graphs;
-    // early exit of chunked relaxations: systems still relaxing after a chunk,
-    // two slots of pinned host memory written by the device, and their events
+    // chunked relaxations: systems still relaxing and systems stalled for a
+    // build after a chunk, two slots of two ints of pinned host memory written
+    // by the device, and their events
     int* act_host = nullptr;
     int* act_dev = nullptr;
     hipEvent_t act_ev[2] = {nullptr, nullptr};
@@ -477,7 +482,7 @@ extern "C" void mxe_plan_destroy(mxe_plan* plan) {
         if (e) (void)hipEventDestroy(e);
     if (plan->act_host) (void)hipHostFree(plan->act_host);
     for (auto& kv : plan->graphs)
-        for (hipGraphExec_t g : {kv.second.step, kv.second.chunk, kv.second.master, kv.second.advance})
+        for (hipGraphExec_t g : kv.second.all())
             if (g) (void)hipGraphExecDestroy(g);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
@@ -682,9 +687,14 @@ void enqueue_eval(mxe_plan* P, const Dev& d, hipStream_t s) {
 }
 
 // One relaxation iteration; free_run (mxe_advance) also takes the Euler step
-// of every system whose relaxation ended in it.
-void enqueue_iteration(mxe_plan* P, const Dev& d, hipStream_t s, bool free_run = false) {
-    timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, false, s); }, true);
+// of every system whose relaxation ended in it. A lean iteration (chunked
+// relaxations) replaces the build chain (8 launches) by one check: a system
+// whose lists expired stalls until an iteration with the chain.
+void enqueue_iteration(mxe_plan* P, const Dev& d, hipStream_t s, bool free_run = false, bool lean = false) {
+    if (lean)
+        timed(P, MXE_K_BUILD, s, [&] { launch_lists_check(d, P->model, s); }, true);
+    else
+        timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, false, s); }, true);
     enqueue_eval(P, d, s);
     timed(P, MXE_K_FIRE, s, [&] {
         launch_control(d, P->model, free_run ? 2 : 1, s);
@@ -708,7 +718,7 @@ void enqueue_diffusion_step(mxe_plan* P, const Dev& d, hipStream_t s) {
 mxe_status ensure_active_slots(mxe_plan* P) {
     if (P->act_host) return MXE_OK;
     int* h = nullptr;
-    HIP_OK(hipHostMalloc((void**)&h, 2 * sizeof(int), hipHostMallocMapped));
+    HIP_OK(hipHostMalloc((void**)&h, 4 * sizeof(int), hipHostMallocMapped));
     void* dp = nullptr;
     hipError_t e = hipHostGetDevicePointer(&dp, h, 0);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&P->act_ev[k], hipEventDisableTiming);
@@ -721,14 +731,15 @@ mxe_status ensure_active_slots(mxe_plan* P) {
         (void)hipHostFree(h);
         return fail(MXE_EDEVICE, std::string("early-exit slots: ") + hipGetErrorString(e));
     }
-    h[0] = h[1] = 1;
+    h[0] = h[2] = 1;
+    h[1] = h[3] = 0;
     P->act_host = h;
     P->act_dev = (int*)dp;
     return MXE_OK;
 }
 
-// Waits (polling) for the event of a slot, then reads its count.
-mxe_status read_active(mxe_plan* P, int slot, int* active) {
+// Waits (polling) for the event of a slot, then reads its counts.
+mxe_status read_active(mxe_plan* P, int slot, int* active, int* stalled) {
     for (;;) {
         const hipError_t e = hipEventQuery(P->act_ev[slot]);
         if (e == hipSuccess) break;
@@ -736,38 +747,53 @@ mxe_status read_active(mxe_plan* P, int slot, int* active) {
         std::this_thread::yield();
     }
     std::atomic_thread_fence(std::memory_order_acquire);
-    *active = ((volatile int*)P->act_host)[slot];
+    *active = ((volatile int*)P->act_host)[2 * slot];
+    *stalled = ((volatile int*)P->act_host)[2 * slot + 1];
     return MXE_OK;
 }
 
-// A relaxation in chunks of relax_chunk iterations (one graph replay each, or
-// eager launches). After every chunk but the last, k_active writes how many
-// systems are still relaxing into a host slot; the host reads chunk c's count
-// after it has enqueued chunk c + 1, so the device never waits for the host,
-// and stops once the count is zero. The chunk enqueued meanwhile runs as a
-// no-op, as do the fixed sequence's iterations after a system has finished.
-mxe_status enqueue_relax_chunked(mxe_plan* P, const Dev& d, hipStream_t s, hipGraphExec_t graph) {
+// A relaxation in chunks of relax_chunk lean iterations (one graph replay each,
+// or eager launches). After every chunk, k_active writes how many systems are
+// still relaxing and how many are stalled for a build into a host slot; the
+// host reads chunk c's counts after it has enqueued chunk c + 1, so the device
+// never waits for the host. It stops once none is relaxing, and enqueues one
+// iteration with the build chain (graph full, or eager) whenever some are
+// stalled: they take it as the iteration they waited for. A stalled system
+// takes no iteration, so the relaxation of each system runs the same FIRE
+// iterations with the same lists as the fixed sequence; chunks enqueued past
+// the end run as no-ops. A system waits at most two chunks per build, which
+// bounds the chunks.
+mxe_status enqueue_relax_chunked(mxe_plan* P, const Dev& d, hipStream_t s, hipGraphExec_t graph,
+                                 hipGraphExec_t full) {
     launch_relax_init(d, P->model, s);
     P->prof_last = -1;
     const int K = P->p.relax_chunk;
-    const int n_chunks = (P->p.max_relax + 1 + K - 1) / K;  // covers max_relax + 1 iterations
-    for (int c = 0; c < n_chunks; ++c) {
+    const int n_cap = 3 * (P->p.max_relax + 1) + 4;
+    bool full_prev = false;  // an iteration with the chain followed chunk c - 1
+    for (int c = 0; c < n_cap; ++c) {
         if (graph) {
             HIP_OK(hipGraphLaunch(graph, s));
         } else {
-            for (int k = 0; k < K; ++k) enqueue_iteration(P, d, s);
+            for (int k = 0; k < K; ++k) enqueue_iteration(P, d, s, false, true);
         }
-        if (c + 1 < n_chunks) {
-            launch_active(d, P->act_dev + (c & 1), 0, s);
-            P->prof_last = -1;  // an untimed launch breaks the chain
-            HIP_OK(hipEventRecord(P->act_ev[c & 1], s));
-        }
+        launch_active(d, P->act_dev + 2 * (c & 1), 0, s);
+        P->prof_last = -1;  // an untimed launch breaks the chain
+        HIP_OK(hipEventRecord(P->act_ev[c & 1], s));
+        bool full_now = false;
         if (c >= 1) {
-            int active = 1;
-            const mxe_status r = read_active(P, (c - 1) & 1, &active);
+            int active = 1, stalled = 0;
+            const mxe_status r = read_active(P, (c - 1) & 1, &active, &stalled);
             if (r != MXE_OK) return r;
             if (active == 0) break;
+            // stalls counted after chunk c - 1 are over once an iteration with
+            // the chain followed it
+            if (stalled > 0 && !full_prev) {
+                if (full) HIP_OK(hipGraphLaunch(full, s));
+                else enqueue_iteration(P, d, s);
+                full_now = true;
+            }
         }
+        full_prev = full_now;
     }
     HIP_OK(hipGetLastError());
     return MXE_OK;
@@ -822,7 +848,7 @@ extern "C" mxe_status mxe_relax(mxe_plan* P, const mxe_state* st, const mxe_out*
     if (P->p.relax_chunk > 0) {
         r = ensure_active_slots(P);
         if (r != MXE_OK) return r;
-        return enqueue_relax_chunked(P, d, s, nullptr);
+        return enqueue_relax_chunked(P, d, s, nullptr, nullptr);
     }
     enqueue_relax(P, d, s);
     HIP_OK(hipGetLastError());
@@ -865,7 +891,7 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
                 enqueue_diffusion_step(P, d, s);
                 continue;
             }
-            r = enqueue_relax_chunked(P, d, s, nullptr);
+            r = enqueue_relax_chunked(P, d, s, nullptr, nullptr);
             if (r != MXE_OK) return r;
             timed(P, MXE_K_MASTER, s, [&] { launch_master(d, P->model, 0.0, s); });
         }
@@ -879,7 +905,7 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
                                           (const void*)(intptr_t)d.n_chunks, (const void*)(intptr_t)d.n_pchunks};
     if (!P->graphs.count(key) && P->graphs.size() >= 16) {  // bounded cache: start afresh
         for (auto& kv : P->graphs)
-            for (hipGraphExec_t g : {kv.second.step, kv.second.chunk, kv.second.master, kv.second.advance})
+            for (hipGraphExec_t g : kv.second.all())
                 if (g) HIP_OK(hipGraphExecDestroy(g));
         P->graphs.clear();
     }
@@ -890,8 +916,10 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
     }
     if (chunked && !G.master) {
         r = capture(P, [&](hipStream_t c) {
-            for (int k = 0; k < P->p.relax_chunk; ++k) enqueue_iteration(P, d, c);
+            for (int k = 0; k < P->p.relax_chunk; ++k) enqueue_iteration(P, d, c, false, true);
         }, &G.chunk);
+        if (r != MXE_OK) return r;
+        r = capture(P, [&](hipStream_t c) { enqueue_iteration(P, d, c); }, &G.full);
         if (r != MXE_OK) return r;
         r = capture(P, [&](hipStream_t c) { launch_master(d, P->model, 0.0, c); }, &G.master);
         if (r != MXE_OK) return r;
@@ -901,7 +929,7 @@ extern "C" mxe_status mxe_run(mxe_plan* P, const mxe_state* st, const mxe_out* o
             HIP_OK(hipGraphLaunch(G.step, s));
             continue;
         }
-        r = enqueue_relax_chunked(P, d, s, G.chunk);
+        r = enqueue_relax_chunked(P, d, s, G.chunk, G.full);
         if (r != MXE_OK) return r;
         HIP_OK(hipGraphLaunch(G.master, s));
     }
@@ -931,7 +959,7 @@ extern "C" mxe_status mxe_advance(mxe_plan* P, const mxe_state* st, const mxe_ou
     r = begin_call(P, d, s, BUILD_LISTS_BONDS, true);
     if (r != MXE_OK) return r;
     const int K = P->p.relax_chunk;
-    hipGraphExec_t g = nullptr;
+    hipGraphExec_t g = nullptr, gf = nullptr;
     if (use_graph && !P->prof_on) {
         const std::vector<const void*> key = {st->qx, st->qy, st->qz, st->sigma, st->x, st->type,
                                               st->reservoir, st->res_value, st->T_site, out->fx, out->fy,
@@ -941,39 +969,51 @@ extern "C" mxe_status mxe_advance(mxe_plan* P, const mxe_state* st, const mxe_ou
                                               (const void*)(intptr_t)d.n_pchunks};
         if (!P->graphs.count(key) && P->graphs.size() >= 16) {  // bounded cache: start afresh
             for (auto& kv : P->graphs)
-                for (hipGraphExec_t e : {kv.second.step, kv.second.chunk, kv.second.master, kv.second.advance})
+                for (hipGraphExec_t e : kv.second.all())
                     if (e) HIP_OK(hipGraphExecDestroy(e));
             P->graphs.clear();
         }
         mxe_plan::Graphs& G = P->graphs[key];
         if (!G.advance) {
             r = capture(P, [&](hipStream_t c) {
-                for (int k = 0; k < K; ++k) enqueue_iteration(P, d, c, true);
+                for (int k = 0; k < K; ++k) enqueue_iteration(P, d, c, true, true);
             }, &G.advance);
+            if (r != MXE_OK) return r;
+            r = capture(P, [&](hipStream_t c) { enqueue_iteration(P, d, c, true); }, &G.advance_full);
             if (r != MXE_OK) return r;
         }
         g = G.advance;
+        gf = G.advance_full;
     }
-    // chunks of K free-running iterations until no system has steps left (read
-    // one chunk behind, as in enqueue_relax_chunked) or max_iters are enqueued
+    // chunks of K lean free-running iterations until no system has steps left
+    // or max_iters are enqueued, with an iteration with the build chain after a
+    // chunk that left systems stalled (both read one chunk behind, as in
+    // enqueue_relax_chunked; stalls seen after the last chunk wait for the next
+    // call)
     const int n_chunks = (max_iters + K - 1) / K;
+    bool full_prev = false;
     for (int c = 0; c < n_chunks; ++c) {
         if (g) {
             HIP_OK(hipGraphLaunch(g, s));
         } else {
-            for (int k = 0; k < K; ++k) enqueue_iteration(P, d, s, true);
+            for (int k = 0; k < K; ++k) enqueue_iteration(P, d, s, true, true);
         }
-        if (c + 1 < n_chunks) {
-            launch_active(d, P->act_dev + (c & 1), 1, s);
-            P->prof_last = -1;
-            HIP_OK(hipEventRecord(P->act_ev[c & 1], s));
-        }
+        launch_active(d, P->act_dev + 2 * (c & 1), 1, s);
+        P->prof_last = -1;
+        HIP_OK(hipEventRecord(P->act_ev[c & 1], s));
+        bool full_now = false;
         if (c >= 1) {
-            int active = 1;
-            r = read_active(P, (c - 1) & 1, &active);
+            int active = 1, stalled = 0;
+            r = read_active(P, (c - 1) & 1, &active, &stalled);
             if (r != MXE_OK) return r;
             if (active == 0) break;
+            if (stalled > 0 && !full_prev) {
+                if (gf) HIP_OK(hipGraphLaunch(gf, s));
+                else enqueue_iteration(P, d, s, true);
+                full_now = true;
+            }
         }
+        full_prev = full_now;
     }
     HIP_OK(hipGetLastError());
     return MXE_OK;

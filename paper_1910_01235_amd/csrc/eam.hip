@@ -475,7 +475,7 @@ void k_pair(Dev d, Model m) {
     // 2^pair_shift blocks share a chunk, each taking a contiguous sub-range
     const Chunk ch = d.pchunks[blockIdx.x >> m.pair_shift];
     const SysCtl& c = d.ctl[ch.sys];
-    if (c.done) return;  // uniform over the block
+    if (idle(c)) return;  // uniform over the block
     const SysDesc& S = d.sys[ch.sys];
     const Box B = box_of(S);
     const int64_t sub = kPairChunk >> m.pair_shift;
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
     const Chunk ch = d.chunks[ub / kGatherSplit];
     constexpr int kPart = kChunk / kGatherSplit;
     const int i_lo = ch.start + (ub % kGatherSplit) * kPart, i_hi = min(ch.end, i_lo + kPart);
-    if (d.ctl[ch.sys].done) return;
+    if (idle(d.ctl[ch.sys])) return;
     const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
     const T* dblk = (const T*)d.dblk;
     const int K = d.K;
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
     const Chunk ch = d.chunks[cb];
     const int i_lo = ch.start + (ub % kForceSplit) * kPart, i_hi = min(ch.end, i_lo + kPart);
     const int sys = ch.sys;
-    if (d.ctl[sys].done) return;
+    if (idle(d.ctl[sys])) return;
     const SysDesc& S = d.sys[sys];
     const double kT = S.kT, T_sys = S.T;
     const bool site_T = d.T_site != nullptr;
@@ -904,7 +904,7 @@ __global__ __launch_bounds__(kChunk) void k_force_fold(Dev d) {
     static_assert(kForceSplit <= kWave && (kForceSplit & (kForceSplit - 1)) == 0, "fold width");
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int cb = t / kForceSplit, k = t % kForceSplit;
-    const bool live = cb < d.n_chunks && !d.ctl[d.chunks[cb < d.n_chunks ? cb : 0].sys].done;
+    const bool live = cb < d.n_chunks && !idle(d.ctl[d.chunks[cb < d.n_chunks ? cb : 0].sys]);
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (live) {
         const double2* R = (const double2*)(d.part_sub + ((int64_t)cb * kForceSplit + k) * kNPart);

@@ -61,7 +61,9 @@ struct SysCtl {
     // free-running steps (mxe_advance): diffusion steps still to run, and the
     // flag that the relaxation ended in this iteration (its Euler step follows)
     int steps_left, stepping;
-    int pad;
+    // lean iterations (chunked relaxations, no build chain): the lists
+    // expired, and the system waits, its iteration not taken, until a build
+    int stall;
 };
 
 struct Chunk {
@@ -315,11 +317,18 @@ void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s);
 void launch_force(const Dev& d, const Model& m, int precision, hipStream_t s);
 void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s);
 void launch_update(const Dev& d, const Model& m, hipStream_t s);
-// systems not done (steps = 0) or with diffusion steps left (steps = 1) -> *out
+// systems not done (steps = 0) or with diffusion steps left (steps = 1) ->
+// out[0], and systems stalled for a build -> out[1]
 void launch_active(const Dev& d, int* out, int steps, hipStream_t s);
+// lean iterations: a system whose lists expired stalls (one thread per system)
+void launch_lists_check(const Dev& d, const Model& m, hipStream_t s);
 // free_run: only systems whose relaxation ended in this iteration step
 void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s, int free_run = 0);
 // relaxation state at the start of a relaxation (FIRE scalars and counters)
+// a system whose iteration is not taken: relaxation finished, or stalled for
+// a build (lean iterations)
+__device__ inline bool idle(const SysCtl& c) { return c.done || c.stall; }
+
 __device__ inline void relax_start(SysCtl& c, const Model& m) {
     c.fire_dt = m.dt0;
     c.fire_alpha = m.alpha0;
@@ -329,6 +338,7 @@ __device__ inline void relax_start(SysCtl& c, const Model& m) {
     c.converged = 0;
     c.updates = 0;
     c.evals = 0;
+    c.stall = 0;
 }
 
 }  // namespace mxe

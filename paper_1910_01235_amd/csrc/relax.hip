@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kChunk) void k_control(Dev d, Model m, int mode) {
     __shared__ double lds[kChunk / kWave];
     const int s = blockIdx.x;
     SysCtl& c = d.ctl[s];
-    if (c.done) return;
+    if (idle(c)) return;
     // a build earlier in this iteration is counted here (the chain's own
     // finishing kernel is not launched within relaxations)
     if (threadIdx.x == 0) finish_build(d, s);
@@ -152,21 +152,35 @@ void launch_control(const Dev& d, const Model& m, int mode, hipStream_t s) {
 }
 
 // Number of systems still relaxing (not done; steps = 0) or with diffusion
-// steps left (steps = 1), written by one block to *out (a host-mapped int): the
-// host reads it between chunks of iterations to stop once it is zero.
+// steps left (steps = 1), and the number stalled for a build, written by one
+// block to out[0] and out[1] (host-mapped ints): the host reads them between
+// chunks of iterations, to stop once the first is zero and to enqueue an
+// iteration with the build chain while the second is not.
 __global__ __launch_bounds__(kChunk) void k_active(const SysCtl* ctl, int n_sys, int steps, int* out) {
-    __shared__ int lds[kChunk / kWave];
-    int n = 0;
-    for (int s = threadIdx.x; s < n_sys; s += blockDim.x)
+    __shared__ int lds[2][kChunk / kWave];
+    int n = 0, st = 0;
+    for (int s = threadIdx.x; s < n_sys; s += blockDim.x) {
         n += (steps ? ctl[s].steps_left > 0 : !ctl[s].done) ? 1 : 0;
+        st += (ctl[s].stall && !ctl[s].done) ? 1 : 0;
+    }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = n;
+    for (int o = 32; o > 0; o >>= 1) {
+        n += __shfl_xor(n, o);
+        st += __shfl_xor(st, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        lds[0][threadIdx.x >> 6] = n;
+        lds[1][threadIdx.x >> 6] = st;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
-        *(volatile int*)out = t;
+        int t = 0, u = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            t += lds[0][w];
+            u += lds[1][w];
+        }
+        ((volatile int*)out)[0] = t;
+        ((volatile int*)out)[1] = u;
     }
 }
 
@@ -181,7 +195,7 @@ __global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
     __shared__ double lds[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
     SysCtl& c = d.ctl[ch.sys];
-    if (c.done) return;
+    if (idle(c)) return;
     const int i = ch.start + threadIdx.x;
     const double dt = c.fire_dt, mv = c.mix_v, mf = c.mix_f;
     const bool keep = c.c_keep != 0.0;
