@@ -142,11 +142,12 @@ typedef struct {
      * the iterations in chunks of K and, after each chunk, reads on the host how
      * many systems are still relaxing; once none is, the relaxation ends after
      * at most one more chunk (read one chunk behind, so the device never waits
-     * for the host). The chunks' iterations are lean: one check of the lists
-     * (7 launches per iteration instead of 14 with the neighbour-build chain);
-     * a system whose lists expired stalls, taking no iteration, and the host
-     * enqueues one iteration with the chain once it reads a stall, after which
-     * the system takes the iteration it waited for. mxe_relax and mxe_run then
+     * for the host). In plans of at most 65,536 occupied sites the chunks'
+     * iterations are lean: one check of the lists (7 launches per iteration
+     * instead of 14 with the neighbour-build chain); a system whose lists
+     * expired stalls, taking no iteration, and the host enqueues one iteration
+     * with the chain once it reads a stall, after which the system takes the
+     * iteration it waited for. Larger plans keep the chain in every iteration. mxe_relax and mxe_run then
      * block the calling thread while they enqueue (the work stays ordered on
      * the caller's stream), and the first such call allocates 16 bytes of
      * pinned host memory and two events that the plan keeps. Results are
@@ -328,10 +329,11 @@ mxe_status mxe_step(mxe_plan* plan, const mxe_state* state, const mxe_out* out, 
  * are built once at the start from the current positions. With use_graph != 0
  * the per-step launch sequence is recorded once into a HIP graph (per plan,
  * buffers and launch extent; at most 16 are kept) and replayed; with
- * params.relax_chunk > 0, graphs of a chunk of relax_chunk lean iterations,
- * of one iteration with the neighbour-build chain and of the Euler step are
- * recorded instead, and each relaxation replays the first until every system
- * has finished, the second after chunks that left systems stalled. */
+ * params.relax_chunk > 0, graphs of a chunk of relax_chunk iterations (lean
+ * ones in small plans, see relax_chunk), of one iteration with the
+ * neighbour-build chain and of the Euler step are recorded instead, and each
+ * relaxation replays the first until every system has finished, the second
+ * after chunks that left systems stalled. */
 mxe_status mxe_run(mxe_plan* plan, const mxe_state* state, const mxe_out* out, int n_steps,
                    int use_graph, void* ws, size_t ws_bytes, void* stream);
 
@@ -347,7 +349,7 @@ mxe_status mxe_run(mxe_plan* plan, const mxe_state* state, const mxe_out* out, i
  *   the next mxe_advance on: its counters and scalars restart, a fresh
  *   relaxation begins, and MXE_S_STEPS_LEFT counts down to 0. A slot never
  *   given a budget has none.
- *   mxe_advance enqueues up to max_iters lean iterations, in chunks of
+ *   mxe_advance enqueues up to max_iters iterations, in chunks of
  *   params.relax_chunk (required > 0), and stops early once no system has
  *   steps left (read on the host one chunk behind; the call waits on the host
  *   between chunks); after a chunk that left systems stalled for a list build

@@ -84,6 +84,17 @@ def test_chunked_run_equals_fixed_sequence(mx, use_graph, chunk):
     say(f"    bitwise equal; evaluations per system {ev.astype(int).tolist()}, builds {builds.tolist()}")
 
 
+def test_chunked_run_large_plan_equals_fixed_sequence(mx):
+    """A plan above the lean-chunk size (65,536 occupied sites) runs its chunks
+    with the build chain in every iteration: bitwise the fixed sequence."""
+    systems = [L.jitter(L.vacancy_bulk(26, 700, 1000.0, 7), 8, xr=(0.3, 0.95))]
+    assert systems[0].n > 65536
+    say(f"[gpu] early exit: one system of {systems[0].n} sites, chunk 4, graph")
+    ref = _run(mx, systems, PARAMS, 2, True)
+    got = _run(mx, systems, dict(PARAMS, relax_chunk=4), 2, True)
+    _same(got, ref, "large plan")
+
+
 def test_chunked_run_exits_early(mx):
     """Counted launches: the chunked run (chunks of lean iterations, and an
     iteration with the build chain after a stall) launches the pair kernel
