@@ -62,10 +62,10 @@ BREAKDOWN_STEPS = 2
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="7391f20978208f2c",
-    pair=dict(fetch_kib=129483.6, write_kib=1019787.0),
-    force=dict(fetch_kib=903346.2, write_kib=14136.0),
-    density=dict(fetch_kib=137329.9, write_kib=27126.5),
+    sources_sha256_16="d0804639f3bf5546",
+    pair=dict(fetch_kib=130685.0, write_kib=1019787.0),
+    force=dict(fetch_kib=903863.6, write_kib=14145.6),
+    density=dict(fetch_kib=137480.7, write_kib=27134.4),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -84,11 +84,11 @@ def counter_traffic(family: str):
 # VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
 # Valid only for the sources they were taken on.
 VALU_COUNTERS = dict(
-    sources_sha256_16="7391f20978208f2c",
-    pair=dict(SQ_INSTS_VALU=209610810.1, SQ_INSTS_VALU_FMA_F64=90583941.8,
-              SQ_INSTS_VALU_MUL_F64=39612898.6, SQ_INSTS_VALU_ADD_F64=9895217.1,
-              SQ_INSTS_VALU_TRANS_F64=3332431.1, SQ_INSTS_VALU_FLOPS_FP64=234009296.5,
-              VALUBusy=85.75, VALUUtilization=85.49),
+    sources_sha256_16="d0804639f3bf5546",
+    pair=dict(SQ_INSTS_VALU=209611814.3, SQ_INSTS_VALU_FMA_F64=90584500.5,
+              SQ_INSTS_VALU_MUL_F64=39613015.4, SQ_INSTS_VALU_ADD_F64=9895266.6,
+              SQ_INSTS_VALU_TRANS_F64=3332424.5, SQ_INSTS_VALU_FLOPS_FP64=234008355.6,
+              VALUBusy=85.18, VALUUtilization=85.48),
 )
 
 
