@@ -689,13 +689,10 @@ void enqueue_eval(mxe_plan* P, const Dev& d, hipStream_t s) {
 
 // One relaxation iteration; free_run (mxe_advance) also takes the Euler step
 // of every system whose relaxation ended in it. A lean iteration (chunked
-// relaxations) replaces the build chain (8 launches) by one check: a system
-// whose lists expired stalls until an iteration with the chain.
+// relaxations of small plans) launches no build chain (8 launches): a system
+// whose lists expired takes no iteration until one with the chain.
 void enqueue_iteration(mxe_plan* P, const Dev& d, hipStream_t s, bool free_run = false, bool lean = false) {
-    if (lean)
-        timed(P, MXE_K_BUILD, s, [&] { launch_lists_check(d, P->model, s); }, true);
-    else
-        timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, false, s); }, true);
+    if (!lean) timed(P, MXE_K_BUILD, s, [&] { launch_build(d, P->model, false, false, s); }, true);
     enqueue_eval(P, d, s);
     timed(P, MXE_K_FIRE, s, [&] {
         launch_control(d, P->model, free_run ? 2 : 1, s);

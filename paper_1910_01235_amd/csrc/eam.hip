@@ -475,7 +475,7 @@ void k_pair(Dev d, Model m) {
     // 2^pair_shift blocks share a chunk, each taking a contiguous sub-range
     const Chunk ch = d.pchunks[blockIdx.x >> m.pair_shift];
     const SysCtl& c = d.ctl[ch.sys];
-    if (idle(c)) return;  // uniform over the block
+    if (idle(c, m)) return;  // uniform over the block
     const SysDesc& S = d.sys[ch.sys];
     const Box B = box_of(S);
     const int64_t sub = kPairChunk >> m.pair_shift;
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(kChunk) void k_density(Dev d, Model m) {
     const Chunk ch = d.chunks[ub / kGatherSplit];
     constexpr int kPart = kChunk / kGatherSplit;
     const int i_lo = ch.start + (ub % kGatherSplit) * kPart, i_hi = min(ch.end, i_lo + kPart);
-    if (idle(d.ctl[ch.sys])) return;
+    if (idle(d.ctl[ch.sys], m)) return;
     const int grp = threadIdx.x / kLPS, sub = threadIdx.x % kLPS;
     const T* dblk = (const T*)d.dblk;
     const int K = d.K;
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
     const Chunk ch = d.chunks[cb];
     const int i_lo = ch.start + (ub % kForceSplit) * kPart, i_hi = min(ch.end, i_lo + kPart);
     const int sys = ch.sys;
-    if (idle(d.ctl[sys])) return;
+    if (idle(d.ctl[sys], m)) return;
     const SysDesc& S = d.sys[sys];
     const double kT = S.kT, T_sys = S.T;
     const bool site_T = d.T_site != nullptr;
@@ -900,11 +900,11 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
 // A site chunk's kForceSplit partial rows summed into the chunk's row, by
 // kForceSplit lanes per chunk with a fixed butterfly order (deterministic).
 // A separate launch: a fence in every force block would write back the L2.
-__global__ __launch_bounds__(kChunk) void k_force_fold(Dev d) {
+__global__ __launch_bounds__(kChunk) void k_force_fold(Dev d, Model m) {
     static_assert(kForceSplit <= kWave && (kForceSplit & (kForceSplit - 1)) == 0, "fold width");
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int cb = t / kForceSplit, k = t % kForceSplit;
-    const bool live = cb < d.n_chunks && !idle(d.ctl[d.chunks[cb < d.n_chunks ? cb : 0].sys]);
+    const bool live = cb < d.n_chunks && !idle(d.ctl[d.chunks[cb < d.n_chunks ? cb : 0].sys], m);
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (live) {
         const double2* R = (const double2*)(d.part_sub + ((int64_t)cb * kForceSplit + k) * kNPart);
@@ -984,7 +984,7 @@ void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s) 
 void launch_force(const Dev& d, const Model& m, int precision, hipStream_t s) {
     if (precision == MXE_FP32_MIXED) launch_force_t<float>(d, m, m.force_lanes, s);
     else launch_force_t<double>(d, m, m.force_lanes, s);
-    k_force_fold<<<(d.n_chunks * kForceSplit + kChunk - 1) / kChunk, kChunk, 0, s>>>(d);
+    k_force_fold<<<(d.n_chunks * kForceSplit + kChunk - 1) / kChunk, kChunk, 0, s>>>(d, m);
 }
 
 }  // namespace mxe

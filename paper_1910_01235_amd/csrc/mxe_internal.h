@@ -61,8 +61,9 @@ struct SysCtl {
     // free-running steps (mxe_advance): diffusion steps still to run, and the
     // flag that the relaxation ended in this iteration (its Euler step follows)
     int steps_left, stepping;
-    // lean iterations (chunked relaxations, no build chain): the lists
-    // expired, and the system waits, its iteration not taken, until a build
+    // lean iterations (chunked relaxations, no build chain): the lists had
+    // expired, so this iteration was not taken (set by k_control each
+    // iteration, read by k_update and by the host's count)
     int stall;
 };
 
@@ -320,14 +321,17 @@ void launch_update(const Dev& d, const Model& m, hipStream_t s);
 // systems not done (steps = 0) or with diffusion steps left (steps = 1) ->
 // out[0], and systems stalled for a build -> out[1]
 void launch_active(const Dev& d, int* out, int steps, hipStream_t s);
-// lean iterations: a system whose lists expired stalls (one thread per system)
-void launch_lists_check(const Dev& d, const Model& m, hipStream_t s);
 // free_run: only systems whose relaxation ended in this iteration step
 void launch_master(const Dev& d, const Model& m, double dt_in, hipStream_t s, int free_run = 0);
 // relaxation state at the start of a relaxation (FIRE scalars and counters)
-// a system whose iteration is not taken: relaxation finished, or stalled for
-// a build (lean iterations)
-__device__ inline bool idle(const SysCtl& c) { return c.done || c.stall; }
+// A system whose iteration is not taken: its relaxation finished, or its
+// lists expired and no build runs in this iteration (a lean iteration; in an
+// iteration with the build chain k_bin has set rebuild). The maxima behind
+// lists_expired change only in k_update, the iteration's last kernel, so
+// every kernel before it reaches the same decision.
+__device__ inline bool idle(const SysCtl& c, const Model& m) {
+    return c.done || (!c.rebuild && lists_expired(c, m));
+}
 
 __device__ inline void relax_start(SysCtl& c, const Model& m) {
     c.fire_dt = m.dt0;

@@ -177,9 +177,6 @@ __device__ inline int block_excl_scan_1024(int v, int* lds, int& total) {
 __global__ __launch_bounds__(kChunk) void k_bin(Dev d, Model m) {
     const Chunk ch = d.chunks[blockIdx.x];
     SysCtl& c = d.ctl[ch.sys];
-    // a system stalled by lean iterations resumes: its lists are rebuilt
-    // below or are valid again (the same write from every block)
-    if (c.stall && threadIdx.x == 0) c.stall = 0;
     if (!c.rebuild) {
         if (!lists_expired(c, m)) return;
         if (threadIdx.x == 0) {  // the same values from every block
@@ -198,21 +195,6 @@ __global__ __launch_bounds__(kChunk) void k_bin(Dev d, Model m) {
     const int64_t cell = site_cell(S, q0, q1, q2);
     d.cell_of[i] = (int)cell;
     d.slot_of[i] = atomicAdd(&d.cell_count[cell], 1);
-}
-
-// Lean iterations (chunked relaxations enqueue no build chain): a system whose
-// lists expired stalls, its evaluation and update not taken, until the host
-// enqueues an iteration with the chain. One thread per system.
-__global__ void k_lists_check(Dev d, Model m) {
-    const int s = gtid();
-    if (s >= d.n_sys) return;
-    SysCtl& c = d.ctl[s];
-    if (c.done || c.stall) return;
-    if (c.rebuild || lists_expired(c, m)) c.stall = 1;
-}
-
-void launch_lists_check(const Dev& d, const Model& m, hipStream_t s) {
-    k_lists_check<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d, m);
 }
 
 // Bins every site for a bonds-only build: the cells as k_bin forms them, but

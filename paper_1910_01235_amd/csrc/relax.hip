@@ -62,10 +62,19 @@ __global__ __launch_bounds__(kChunk) void k_control(Dev d, Model m, int mode) {
     __shared__ double lds[kChunk / kWave];
     const int s = blockIdx.x;
     SysCtl& c = d.ctl[s];
-    if (idle(c)) return;
+    if (c.done) return;
+    // a lean iteration whose lists had expired: not taken (k_update reads the
+    // flag, as its own blocks move the maxima the decision rests on)
+    if (idle(c, m)) {
+        if (threadIdx.x == 0) c.stall = 1;
+        return;
+    }
     // a build earlier in this iteration is counted here (the chain's own
     // finishing kernel is not launched within relaxations)
-    if (threadIdx.x == 0) finish_build(d, s);
+    if (threadIdx.x == 0) {
+        c.stall = 0;
+        finish_build(d, s);
+    }
     const SysDesc& S = d.sys[s];
     if (S.n_sites == 0) {  // an empty slot evaluates nothing and counts nothing
         if (threadIdx.x == 0) {
@@ -195,7 +204,7 @@ __global__ __launch_bounds__(kChunk) void k_update(Dev d, Model m) {
     __shared__ double lds[kChunk / kWave];
     const Chunk ch = d.chunks[blockIdx.x];
     SysCtl& c = d.ctl[ch.sys];
-    if (idle(c)) return;
+    if (c.done || c.stall) return;  // as k_control decided for this iteration
     const int i = ch.start + threadIdx.x;
     const double dt = c.fire_dt, mv = c.mix_v, mf = c.mix_f;
     const bool keep = c.c_keep != 0.0;
