@@ -62,10 +62,10 @@ BREAKDOWN_STEPS = 2
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="d0804639f3bf5546",
-    pair=dict(fetch_kib=130685.0, write_kib=1019787.0),
-    force=dict(fetch_kib=903863.6, write_kib=14145.6),
-    density=dict(fetch_kib=137480.7, write_kib=27134.4),
+    sources_sha256_16="7d0a53f8dd44c272",
+    pair=dict(fetch_kib=129593.4, write_kib=1019787.0),
+    force=dict(fetch_kib=903639.1, write_kib=14143.1),
+    density=dict(fetch_kib=137338.3, write_kib=27114.5),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -84,11 +84,11 @@ def counter_traffic(family: str):
 # VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
 # Valid only for the sources they were taken on.
 VALU_COUNTERS = dict(
-    sources_sha256_16="d0804639f3bf5546",
-    pair=dict(SQ_INSTS_VALU=209611814.3, SQ_INSTS_VALU_FMA_F64=90584500.5,
-              SQ_INSTS_VALU_MUL_F64=39613015.4, SQ_INSTS_VALU_ADD_F64=9895266.6,
-              SQ_INSTS_VALU_TRANS_F64=3332424.5, SQ_INSTS_VALU_FLOPS_FP64=234008355.6,
-              VALUBusy=85.18, VALUUtilization=85.48),
+    sources_sha256_16="7d0a53f8dd44c272",
+    pair=dict(SQ_INSTS_VALU=210143275.1, SQ_INSTS_VALU_FMA_F64=90736210.3,
+              SQ_INSTS_VALU_MUL_F64=39669894.8, SQ_INSTS_VALU_ADD_F64=9895193.7,
+              SQ_INSTS_VALU_TRANS_F64=3351460.1, SQ_INSTS_VALU_FLOPS_FP64=234387631.3,
+              VALUBusy=85.95, VALUUtilization=85.50),
 )
 
 
@@ -280,10 +280,11 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
     single server.
 
     Two schedules: relaxations that end once every system of the plan has
-    converged (relax_chunk > 0; the one-at-a-time path with launch shapes tuned
-    per size octave), and the fixed sequence of max_relax + 1 iterations per
-    relaxation with the batch's shapes everywhere (`fixed_sequence`, at the
-    same absolute arrival rates for before_rates). The server runs at the
+    converged (relax_chunk > 0), and the fixed sequence of max_relax + 1
+    iterations per relaxation (`fixed_sequence`, at the same absolute arrival
+    rates for before_rates). Both schedules use the same launch shapes: tuned
+    on the batch for the batched runs, per size octave for the one-at-a-time
+    runs, and on eight requests over the size range for the server. The server runs at the
     iteration level (free-running steps, `served`) and, for before_rates, at
     the step level (`served_step_level`: one diffusion step of every resident
     system per call)."""
@@ -405,11 +406,13 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
     # fixed sequence, same absolute arrival rates
     bat0, x_b0 = batched(params)
     log(f"serving: batched, fixed sequence {bat0['wall_s']:.1f} s")
-    one0, service0, res0 = one_at_a_time(params, None, "fixed sequence")
-    srv0, _, _ = served(params, [(f, f * cap) for f in before_rates], service0, "fixed sequence")
-    # the three batched runs (free-running, lockstep, fixed sequence) differ only
-    # in the schedule: bitwise equal; the one-at-a-time runs also differ in
-    # launch shapes (lanes per site reorder sums): to rounding
+    one0, service0, res0 = one_at_a_time(params, lambda s: dict(single[id(s)], relax_chunk=0),
+                                         "fixed sequence")
+    srv0, _, _ = served(dict(params_pool, relax_chunk=0), [(f, f * cap) for f in before_rates],
+                        service0, "fixed sequence")
+    # each pair of runs (batched free-running, lockstep and fixed sequence; one
+    # at a time early exit and fixed sequence) has the same launch shapes and
+    # differs only in the schedule
     same = all(np.array_equal(a, b) and np.array_equal(a, c) for a, b, c in zip(x_b, x_b0, x_l))
     dx = max(float(np.abs(a.x - b.x).max()) for a, b in zip(sorted(res1, key=lambda r: r.rid),
                                                             sorted(res0, key=lambda r: r.rid)))

@@ -7,7 +7,11 @@ size of the pair quadrature kernel (64, 128, 256) and its blocks per chunk of
 gathers' chunk visit stride. The tuner times every candidate on the workload at hand (HIP
 events around each kernel launch, through the library's profiling switch),
 keeps the fastest of each, and caches the choice per size bucket, precision
-and lattice kind in a JSON file.
+and lattice kind in a JSON file. Pair blocks within 3 % of the fastest count as
+tied and the largest of them is kept: the grid has a fixed number of blocks
+per chunk, so a smaller block means fewer threads per launch, which a large
+batch hides and a plan of a few chunks does not (one small system with the
+64-thread block of a large batch's tie takes half as long again per step).
 
 Stride candidates come from the systems' own site order: the index distance
 from a site to its nearest neighbours one lattice layer away, in chunks of
@@ -27,6 +31,7 @@ GATHER_LANES = (8, 16, 32, 64)
 CHUNK = 256  # sites per chunk of the gathers
 PAIR_BLOCKS = (64, 128, 256)
 PAIR_SPLITS = (1, 2, 4, 8, 16)
+PAIR_BLOCK_TIE = 0.03  # relative time within which pair blocks count as tied
 SHAPES = ("gather_lanes", "force_lanes", "pair_block", "pair_split", "gather_stride")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mxe_autotune.json")
 
@@ -118,7 +123,8 @@ def tune(systems, eam: dict, params: dict, precision: str = "fp64", reps: int = 
         timings["pair_block"][b] = ms["pair"]
     best_g = min(timings["gather_lanes"], key=timings["gather_lanes"].get)
     best_f = min(timings["force_lanes"], key=timings["force_lanes"].get)
-    best_b = min(timings["pair_block"], key=timings["pair_block"].get)
+    t_b = min(timings["pair_block"].values())
+    best_b = max(b for b, t in timings["pair_block"].items() if t <= t_b * (1.0 + PAIR_BLOCK_TIE))
     for sp in PAIR_SPLITS:  # with the tuned block
         ms = _time_kernels(systems, eam, params, precision, reps, pair_block=best_b, pair_split=sp)
         timings["pair_split"][sp] = ms["pair"]

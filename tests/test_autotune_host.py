@@ -71,3 +71,18 @@ def test_profile_modes_are_validated():
     plan.profile("pair")
     plan.profile(True)
     plan.profile(False)
+
+
+@pytest.mark.parametrize("t64,expect", [(0.99, 256), (0.90, 64), (1.02, 256)])
+def test_pair_block_near_ties_keep_the_largest(monkeypatch, t64, expect):
+    """Pair blocks within the tie margin of the fastest: the largest is kept
+    (more threads per chunk); a clearly faster smaller block still wins."""
+    def fake(systems, eam, params, precision, reps, **shape):
+        b = shape.get("pair_block", 256)
+        pair = {64: t64, 128: 1.005, 256: 1.0}[b] * (1.0 + 0.01 * shape.get("pair_split", 1))
+        return dict(density=1.0, force=1.0, pair=pair)
+    monkeypatch.setattr(autotune, "_time_kernels", fake)
+    w = L.config0(0)
+    got = autotune.tune(w.systems, w.eam, w.params, reps=1)
+    assert got["pair_block"] == expect
+    assert got["pair_split"] == 1
