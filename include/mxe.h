@@ -143,8 +143,8 @@ typedef struct {
      * many systems are still relaxing; once none is, the relaxation ends after
      * at most one more chunk (read one chunk behind, so the device never waits
      * for the host). In plans of at most 65,536 occupied sites the chunks'
-     * iterations are lean: no neighbour-build chain (6 launches per iteration
-     * instead of 14); a system whose lists expired stalls, taking no
+     * iterations are lean: no neighbour-build chain (5 launches per iteration
+     * instead of 13); a system whose lists expired stalls, taking no
      * iteration, and the host enqueues one iteration with the chain once it
      * reads a stall, after which the system takes the iteration it waited for.
      * Larger plans keep the chain in every iteration. mxe_relax and mxe_run then

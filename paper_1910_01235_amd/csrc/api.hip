@@ -425,6 +425,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
     }
     for (int s = 0; s < n_systems; ++s) bind_slot(P, s, systems[s], false);
     order_tables(P);
+    for (int s = 0; s < n_systems; ++s) m.fold_rows |= P->sys[s].n_chunks > kChunk;
 
     // workspace layout
     const size_t A = 256;

@@ -709,7 +709,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
     constexpr int kGroups = kChunk / kLPS;
     __shared__ double red[kGroups][6];
     // kForceSplit blocks per site chunk, each taking a contiguous part of it
-    // and writing its own partial row (k_force_fold combines a chunk's rows)
+    // and writing its own partial row (combined per chunk by k_force_fold or the FIRE control)
     const int ub = xcd_unit_strided(d.n_chunks, kForceSplit, m.gather_stride);
     if (ub >= d.n_chunks * kForceSplit) return;
     const int cb = ub / kForceSplit;
@@ -898,8 +898,10 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(4))) voi
 }
 
 // A site chunk's kForceSplit partial rows summed into the chunk's row, by
-// kForceSplit lanes per chunk with a fixed butterfly order (deterministic).
-// A separate launch: a fence in every force block would write back the L2.
+// kForceSplit lanes per chunk with a fixed butterfly order (the order the FIRE
+// control uses when it folds the rows itself). Launched for plans with a
+// system of more chunks than the control block has threads; a fence in every
+// force block instead would write back the L2.
 __global__ __launch_bounds__(kChunk) void k_force_fold(Dev d, Model m) {
     static_assert(kForceSplit <= kWave && (kForceSplit & (kForceSplit - 1)) == 0, "fold width");
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -984,7 +986,7 @@ void launch_density(const Dev& d, const Model& m, int precision, hipStream_t s) 
 void launch_force(const Dev& d, const Model& m, int precision, hipStream_t s) {
     if (precision == MXE_FP32_MIXED) launch_force_t<float>(d, m, m.force_lanes, s);
     else launch_force_t<double>(d, m, m.force_lanes, s);
-    k_force_fold<<<(d.n_chunks * kForceSplit + kChunk - 1) / kChunk, kChunk, 0, s>>>(d, m);
+    if (m.fold_rows) k_force_fold<<<(d.n_chunks * kForceSplit + kChunk - 1) / kChunk, kChunk, 0, s>>>(d, m);
 }
 
 }  // namespace mxe

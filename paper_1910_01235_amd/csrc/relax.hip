@@ -54,6 +54,37 @@ void launch_relax_init(const Dev& d, const Model& m, hipStream_t s) {
     k_relax_init<<<(d.n_sys + 63) / 64, 64, 0, s>>>(d, m);
 }
 
+// The force gather's partial sums of site chunk cb (energy, largest force
+// component, F.v, F.F, v.v, sum of x): folded already (fold_rows), or its
+// kForceSplit rows combined here, pairwise with the lower half first.
+__device__ inline void chunk_row(const Dev& d, const Model& m, int cb, double v[6]) {
+    static_assert(kForceSplit >= 2 && (kForceSplit & (kForceSplit - 1)) == 0, "fold width");
+    if (m.fold_rows) {
+        const double* P = d.part + (int64_t)cb * kNPart;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) v[j] = P[j];
+        return;
+    }
+    const double2* R = (const double2*)(d.part_sub + (int64_t)cb * kForceSplit * kNPart);
+    double r[kForceSplit][6];
+#pragma unroll
+    for (int k = 0; k < kForceSplit; ++k) {
+        const double2 a = R[k * (kNPart / 2)], b = R[k * (kNPart / 2) + 1], c = R[k * (kNPart / 2) + 2];
+        r[k][0] = a.x, r[k][1] = a.y, r[k][2] = b.x, r[k][3] = b.y, r[k][4] = c.x, r[k][5] = c.y;
+    }
+#pragma unroll
+    for (int w = 1; w < kForceSplit; w <<= 1) {
+#pragma unroll
+        for (int k = 0; k < kForceSplit; k += 2 * w) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+                r[k][j] = j == P_FMAX ? fmax(r[k][j], r[k + w][j]) : r[k][j] + r[k + w][j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) v[j] = r[0][j];
+}
+
 // One block per system: reduce the chunk partials in chunk order, then run
 // the FIRE decision (mode 1) or only record the evaluation (mode 0). Mode 2
 // (free-running steps) is mode 1 where a system whose relaxation ends with
@@ -83,15 +114,21 @@ __global__ __launch_bounds__(kChunk) void k_control(Dev d, Model m, int mode) {
         }
         return;
     }
+    // each chunk's row of partial sums (its kForceSplit force-gather rows
+    // combined pairwise in a fixed order), then the chunks in thread order. A
+    // plan with a system of more chunks than this block has threads has the
+    // rows folded by k_force_fold (many blocks, the same order): one block
+    // reading eight rows per chunk of a large system waits on too many misses.
     double e = 0.0, fm = 0.0, fv = 0.0, ff = 0.0, vv = 0.0, sx = 0.0;
     for (int k = threadIdx.x; k < S.n_chunks; k += blockDim.x) {
-        const double* P = d.part + (int64_t)(S.chunk_first + k) * kNPart;
-        e += P[P_E];
-        fm = fmax(fm, P[P_FMAX]);
-        fv += P[P_FV];
-        ff += P[P_FF];
-        vv += P[P_VV];
-        sx += P[P_SUMX];
+        double v[6];
+        chunk_row(d, m, S.chunk_first + k, v);
+        e += v[P_E];
+        fm = fmax(fm, v[P_FMAX]);
+        fv += v[P_FV];
+        ff += v[P_FF];
+        vv += v[P_VV];
+        sx += v[P_SUMX];
     }
     e = block_sum(e, lds);
     fm = block_max(fm, lds);

@@ -184,3 +184,29 @@ def test_gather_stride_and_pair_split_keep_results_bitwise(mx, precision):
             for a, b in zip(got, ref):
                 assert np.array_equal(a, b), (precision, len(systems), shape)
 
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_row_fold_paths_agree_bitwise(mx, precision):
+    """The FIRE control folds the force gather's partial rows itself, unless a
+    system of the plan has more than 256 site chunks (then a launch of its own
+    folds them, in the same order): a small system gives the same bits alone
+    and beside a 70k-site system."""
+    small = L.vacancy_bulk(6, 1, 900.0, 5, name="vac6")
+    big = L.vacancy_bulk(26, 700, 1000.0, 7, name="vac26")
+    assert big.n > 256 * 256
+    params = dict(L.DEFAULT_PARAMS, max_relax=12)
+    say(f"[gpu] row fold paths {precision}: {small.n} alone and beside {big.n}")
+    x, q, sg, sc1 = _run_alone(mx, small, params, 2, precision)
+    plan = mx.Plan([big, small], L.DEFAULT_EAM, params, precision=precision)
+    st, out, ws = plan.state([big, small]), plan.out(), plan.workspace()
+    plan.run(st, out, ws, 2, use_graph=True)
+    torch.cuda.synchronize()
+    lo, hi = plan.offsets[1], plan.offsets[2]
+    sc = plan.scalars(out)
+    assert np.array_equal(st.x[lo:hi].cpu().numpy(), x)
+    assert np.array_equal(st.sigma[lo:hi].cpu().numpy(), sg)
+    assert np.array_equal(st.qx[lo:hi].cpu().numpy(), q[:, 0])
+    for key in (mx.S_TIME, mx.S_F, mx.S_FMAX, mx.S_SUMX, mx.S_UPDATES):
+        assert sc[1, key] == sc1[key], key
+    assert int(sc[0, mx.S_STATUS]) & mx.FATAL_STATUS == 0
