@@ -142,8 +142,8 @@ typedef struct {
      * the iterations in chunks of K and, after each chunk, reads on the host how
      * many systems are still relaxing; once none is, the relaxation ends after
      * at most one more chunk (read one chunk behind, so the device never waits
-     * for the host). In plans of at most 65,536 occupied sites the chunks'
-     * iterations are lean: no neighbour-build chain (5 launches per iteration
+     * for the host). In plans of one occupied system, or of at most 65,536
+     * occupied sites, the chunks' iterations are lean: no neighbour-build chain (5 launches per iteration
      * instead of 13); a system whose lists expired stalls, taking no
      * iteration, and the host enqueues one iteration with the chain once it
      * reads a stall, after which the system takes the iteration it waited for.

@@ -65,6 +65,7 @@ struct mxe_plan {
     // chunk tables hold the occupied slots' chunks first; launches cover that
     // prefix (rounded up to a power of two)
     int64_t live_chunks = 0, live_pchunks = 0;
+    int live_sys = 0;  // occupied slots
     // graph cache for mxe_run, per buffers and launch extents: one diffusion
     // step, or (relax_chunk > 0) a chunk of lean relaxation iterations, one
     // iteration with the build chain and the Euler step; mxe_advance's chunk
@@ -125,6 +126,7 @@ void order_tables(mxe_plan* P) {
     P->chunks.clear();
     P->pchunks.clear();
     P->live_chunks = P->live_pchunks = 0;
+    P->live_sys = 0;
     for (int pass = 0; pass < 2; ++pass)
         for (int s = 0; s < P->n_sys; ++s) {
             SysDesc& d = P->sys[s];
@@ -139,6 +141,7 @@ void order_tables(mxe_plan* P) {
                 P->pchunks.push_back(Chunk{s, (int)(d.pair_base + a),
                                            (int)(d.pair_base + std::min<int64_t>(d.pair_cap, a + kPairChunk)), 0});
             if (pass == 0) {
+                P->live_sys += 1;
                 P->live_chunks = (int64_t)P->chunks.size();
                 P->live_pchunks = (int64_t)P->pchunks.size();
             }
@@ -751,16 +754,19 @@ mxe_status read_active(mxe_plan* P, int slot, int* active, int* stalled) {
     return MXE_OK;
 }
 
-// Lean chunks for plans of at most this many occupied sites. A stalled system
-// waits up to two chunks for its build (the host reads one chunk behind): in a
-// plan of many systems some system stalls in nearly every chunk, and the
-// build chain's early-exit launches, which lean iterations save, are a small
-// share of a large plan's iteration. Measured on the 256 serving-mix requests
-// (500 to 48,668 sites): one at a time 10.3 -> 9.1 s with lean chunks, all in
-// one plan 4.35 -> 4.7 s.
+// Lean chunks for plans of one occupied system or of at most this many
+// occupied sites. A stalled system waits up to two chunks for its build (the
+// host reads one chunk behind): in a plan of many systems some system stalls in
+// nearly every chunk, and the build chain's early-exit launches, which lean
+// iterations save, are a small share of a large plan's iteration. Measured on
+// the 256 serving-mix requests (500 to 48,668 sites): one at a time 10.3 ->
+// 9.1 s with lean chunks, all in one plan 4.35 -> 4.7 s; the 256k-site vacancy
+// lattice alone, eager, chunks of 2: 33.3 -> 33.1 ms per step.
 constexpr int64_t kLeanMaxSites = 65536;
 
-bool lean_chunks(const mxe_plan* P) { return P->live_chunks * (int64_t)kChunk <= kLeanMaxSites; }
+bool lean_chunks(const mxe_plan* P) {
+    return P->live_sys <= 1 || P->live_chunks * (int64_t)kChunk <= kLeanMaxSites;
+}
 
 // A relaxation in chunks of relax_chunk iterations, lean ones for small plans
 // (one graph replay each, or eager launches). After every chunk, k_active writes how many systems are

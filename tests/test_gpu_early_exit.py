@@ -84,12 +84,16 @@ def test_chunked_run_equals_fixed_sequence(mx, use_graph, chunk):
     say(f"    bitwise equal; evaluations per system {ev.astype(int).tolist()}, builds {builds.tolist()}")
 
 
-def test_chunked_run_large_plan_equals_fixed_sequence(mx):
-    """A plan above the lean-chunk size (65,536 occupied sites) runs its chunks
-    with the build chain in every iteration: bitwise the fixed sequence."""
+@pytest.mark.parametrize("companion", [False, True])
+def test_chunked_run_large_plan_equals_fixed_sequence(mx, companion):
+    """Above 65,536 occupied sites, a plan of one system still runs lean
+    iterations; with a second system its chunks carry the build chain in every
+    iteration. Both: bitwise the fixed sequence."""
     systems = [L.jitter(L.vacancy_bulk(26, 700, 1000.0, 7), 8, xr=(0.3, 0.95))]
+    if companion:
+        systems.append(L.jitter(L.vacancy_bulk(5, 1, 800.0, 9), 10, xr=(0.3, 0.95)))
     assert systems[0].n > 65536
-    say(f"[gpu] early exit: one system of {systems[0].n} sites, chunk 4, graph")
+    say(f"[gpu] early exit: {len(systems)} system(s), {sum(t.n for t in systems)} sites, chunk 4, graph")
     ref = _run(mx, systems, PARAMS, 2, True)
     got = _run(mx, systems, dict(PARAMS, relax_chunk=4), 2, True)
     _same(got, ref, "large plan")
