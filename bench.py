@@ -262,7 +262,7 @@ def sampled_errors(workload, plan, st, out, ws, precision, n_sample=64, seed=0):
 
 
 RELAX_CHUNK_BATCHED = 4   # relaxation chunk of the batched plan and the server pool
-RELAX_CHUNK_SINGLE = 2    # and of the one-at-a-time path (small systems, short chunks)
+RELAX_CHUNK_SINGLE = 2    # and of single-system plans (one-at-a-time requests, full runs)
 ADVANCE_ITERS = 8         # iterations per call of the iteration-level server
 
 
@@ -521,7 +521,10 @@ def fullsize_leg(w, precision, steps, warmup, quad_rule=0, params=None, late=0):
 def full_run_leg(w, precision, params=None):
     """A workload's whole configured run (all its diffusion steps) as one call
     of graph replays: the end-to-end wall time, with the state uploaded first
-    (not timed)."""
+    (not timed). Relaxations run in chunks of RELAX_CHUNK_SINGLE lean
+    iterations and end once the system has converged (bitwise the fixed
+    sequence's results; the alloy slab's relaxations converge within 30
+    updates from about step 200)."""
     import torch
 
     from paper_1910_01235_amd import mxe
@@ -531,6 +534,7 @@ def full_run_leg(w, precision, params=None):
     else:
         from paper_1910_01235_amd import autotune
         shapes = {k: params.get(k) for k in autotune.SHAPES}
+    params = dict(params, relax_chunk=RELAX_CHUNK_SINGLE)
     plan = mxe.Plan([s], w.eam, params, precision=precision)
     st, out, ws = plan.state([s]), plan.out(), plan.workspace()
     wall, sc, _ = timed_run(plan, st, out, ws, w.n_steps, use_graph=True, profile=False)
@@ -540,7 +544,8 @@ def full_run_leg(w, precision, params=None):
                wall_s=wall, evals=ev, value=s.n * ev / wall, unit="site-evals/s",
                site_steps_per_s=n_mobile * w.n_steps / wall, list_builds=int(sc[mxe.S_REBUILDS]),
                simulated_time_s=float(sc[mxe.S_TIME]), status=int(sc[mxe.S_STATUS]),
-               launch="one call, graph replays")
+               launch=f"one call, graph replays; relaxations in chunks of {RELAX_CHUNK_SINGLE} "
+                      "iterations ending once converged")
     del st, out, ws, plan
     torch.cuda.empty_cache()
     return res
