@@ -322,8 +322,8 @@ def serving_sweep(n_requests: int, n_steps: int, rate_factors, seed: int = 4,
         """All requests in one plan: lockstep steps (mxe_run) or free-running
         steps (mxe_advance, each system stepping as soon as it has relaxed).
         Each run times the whole job from plan creation on; the faster of
-        `runs` runs is reported (the first run after the tuner has once
-        taken a second longer than the same job run again), with every
+        `runs` runs is reported (an occasional free-running run has taken
+        about a second longer than the same job run again), with every
         run's wall time."""
         walls, xs = [], []
         for _ in range(runs):
