@@ -174,9 +174,11 @@ template <> struct Math<float> {
     static __device__ inline float rsq(float v) { return __frsqrt_rn(v); }
     static __device__ inline void taper(float d, const ShapeK<float>& k, float& S, float& sn,
                                         const PolyCoef&) {
-        float c;
-        sincospif(d * k.tw, &sn, &c);
-        S = 0.5f * (1.0f + c);
+        // sin(pi x), cos(pi x) for x = d / width in [0, 1]; the hardware sine
+        // and cosine take turns (sin(2 pi y)), so y = x / 2 in [0, 1/2]
+        const float y = 0.5f * d * k.tw;
+        sn = __builtin_amdgcn_sinf(y);
+        S = 0.5f * (1.0f + __builtin_amdgcn_cosf(y));
     }
 };
 
