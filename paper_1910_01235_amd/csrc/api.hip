@@ -356,6 +356,7 @@ extern "C" mxe_status mxe_plan_create(const mxe_params* params, const mxe_eam* e
                 if (std::fabs(al * q - ga * pp) <= 1e-12 * std::fmax(std::fabs(al), std::fabs(ga)) && al > 0 &&
                     ga > 0)
                     m.ratio_pq[c] = pp * 16 + q;
+        m.u_rate[c] = m.ratio_pq[c] ? m.alpha[c] / (double)(m.ratio_pq[c] >> 4) : 0.0;
     }
     m.quad_rule = p.quad_rule;
     // near-minimax remainder polynomials of node_poly.h

@@ -145,7 +145,9 @@ __device__ inline ShapeK<T> shape_consts(const Model& m, int cls) {
     k.u1 = k.u0 = T(0);
     k.second = kPQ1 != kPQ && cls != 0;
     if constexpr (kPQ != 0) {
-        const double g = al / (k.second ? kRatioP<kPQ1> : kRatioP<kPQ>);
+        // alpha / P of the pair's class (the kernels are compiled for the
+        // plan's ratio codes), selected like the other class values
+        const double g = c1 ? m.u_rate[1] : m.u_rate[0];
         k.u1 = (T)(-g * ir * kLog2e);
         k.u0 = (T)(g * kLog2e);
     }
@@ -405,7 +407,7 @@ __device__ inline void pair_moments_d3(const Model& m, int cls, double rx, doubl
 // through the system record inside the loop, the compiler reloads it after
 // every store (it may alias) and waits for every load in flight.
 struct Box {
-    double len[3];
+    double len[3], inv[3];  // lengths and their reciprocals
     bool periodic[3];
 };
 
@@ -413,15 +415,29 @@ __device__ inline Box box_of(const SysDesc& S) {
     Box b;
     for (int k = 0; k < 3; ++k) {
         b.len[k] = S.box[k];
+        b.inv[k] = 1.0 / S.box[k];
         b.periodic[k] = S.periodic[k] != 0;
     }
     return b;
 }
 
+// kRcp: the image multiple by the reciprocal length. It differs from the
+// quotient's rounding only within an ulp of a half-integer, i.e. for a
+// separation of half a box, which no listed pair has (lists reach less than
+// half a box), so the results are the same. The FP32-mixed kernels take it
+// (three divisions fewer per pair); the FP64 kernels, at their register limit,
+// would spill the three reciprocals and keep the division.
+template <bool kRcp>
 __device__ inline void min_image(const Box& B, double& dx, double& dy, double& dz) {
-    if (B.periodic[0]) dx -= B.len[0] * rint(dx / B.len[0]);
-    if (B.periodic[1]) dy -= B.len[1] * rint(dy / B.len[1]);
-    if (B.periodic[2]) dz -= B.len[2] * rint(dz / B.len[2]);
+    if (kRcp) {
+        if (B.periodic[0]) dx -= B.len[0] * rint(dx * B.inv[0]);
+        if (B.periodic[1]) dy -= B.len[1] * rint(dy * B.inv[1]);
+        if (B.periodic[2]) dz -= B.len[2] * rint(dz * B.inv[2]);
+    } else {
+        if (B.periodic[0]) dx -= B.len[0] * rint(dx / B.len[0]);
+        if (B.periodic[1]) dy -= B.len[1] * rint(dy / B.len[1]);
+        if (B.periodic[2]) dz -= B.len[2] * rint(dz / B.len[2]);
+    }
 }
 
 }  // namespace
@@ -443,7 +459,7 @@ __device__ inline void pair_all_moments(const Model& m, const Box& B, double rx,
                                         double rz, double si, double sj, int cls, T out[kFBlk]) {
 #pragma unroll
     for (int k = 0; k < kFBlk; ++k) out[k] = T(0);
-    min_image(B, rx, ry, rz);
+    min_image<sizeof(T) == sizeof(float)>(B, rx, ry, rz);
     const double s = sqrt(si * si + sj * sj);
     // a pair contributes iff some node lies inside r_c: the farthest node is
     // 3 s from rbar under the product rule, sqrt(6) max(sigma) under degree 3

@@ -105,6 +105,7 @@ struct Model {
     int gather_stride;             // chunk visit stride of the gathers (xcd_unit_strided)
     int pair_shift;                // log2 of the pair-kernel blocks per pair chunk
     int ratio_pq[2];               // per class: 16 P + Q when alpha : gamma = P : Q (P, Q <= 15), else 0
+    double u_rate[2];              // per class with a ratio: alpha / P (divided on the host, not per pair)
     int fold_rows;                 // a system has more site chunks than the FIRE control has threads:
                                    // the force gather's partial rows are folded per chunk by a launch of their own
 };
