@@ -62,10 +62,10 @@ BREAKDOWN_STEPS = 2
 # the kernel sources they were taken on: a different source hash reports null.
 COUNTER_SCALE = dict(fetch=2.000, write=1.000)
 COUNTERS = dict(
-    sources_sha256_16="c5443481dc98fa53",
-    pair=dict(fetch_kib=129221.6, write_kib=1019787.0),
-    force=dict(fetch_kib=903684.5, write_kib=14140.2),
-    density=dict(fetch_kib=137344.3, write_kib=27112.3),
+    sources_sha256_16="2ff4811c22563528",
+    pair=dict(fetch_kib=130086.8, write_kib=1019787.0),
+    force=dict(fetch_kib=903744.1, write_kib=14186.7),
+    density=dict(fetch_kib=137313.9, write_kib=27112.3),
 )
 COUNTER_SOURCES = ("paper_1910_01235_amd/csrc/eam.hip", "paper_1910_01235_amd/csrc/mxe_internal.h")
 
@@ -84,11 +84,11 @@ def counter_traffic(family: str):
 # VALUBusy and VALUUtilization are rocprofv3's derived metrics (percent).
 # Valid only for the sources they were taken on.
 VALU_COUNTERS = dict(
-    sources_sha256_16="c5443481dc98fa53",
-    pair=dict(SQ_INSTS_VALU=210143013.4, SQ_INSTS_VALU_FMA_F64=90735987.3,
-              SQ_INSTS_VALU_MUL_F64=39669853.9, SQ_INSTS_VALU_ADD_F64=9895221.9,
-              SQ_INSTS_VALU_TRANS_F64=3351476.9, SQ_INSTS_VALU_FLOPS_FP64=234389375.0,
-              VALUBusy=85.82, VALUUtilization=85.50),
+    sources_sha256_16="2ff4811c22563528",
+    pair=dict(SQ_INSTS_VALU=209732141.5, SQ_INSTS_VALU_FMA_F64=90076895.5,
+              SQ_INSTS_VALU_MUL_F64=39560002.8, SQ_INSTS_VALU_ADD_F64=9895188.5,
+              SQ_INSTS_VALU_TRANS_F64=3241630.5, SQ_INSTS_VALU_FLOPS_FP64=232852358.8,
+              VALUBusy=85.53, VALUUtilization=85.24),
 )
 
 
